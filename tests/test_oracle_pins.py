@@ -1,0 +1,396 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside the oracle itself:
+library routines (numpy/LAPACK), closed forms derived by hand (tests/golden),
+brute-force enumeration, the paper's theorems and algebraic invariants.
+
+Citations are to arXiv 2502.11017: Def. 1 (volume), Sec. 1.2 (maximal-volume
+problem), Thm 1 / Thm 2 (Chebyshev error bounds), Alg. 1 (ACA), Alg. 3
+(blockwise selection, strict '>' scan), Sec. 3.1 (Frobenius relative error,
+Hilbert and 1/(i+j) test matrices).
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2502_11017_amd import workloads as W
+from tests.helpers import (EPS, brute_force_maxvol, col_interp, rand, root_candidates,
+                           row_interp, single_swap_gain, trace_logvol)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- GEPP / inverse / volume
+def test_gepp_hand_example(orc):
+    # [[1,2],[3,4]]: |3| > |1| so row 1 pivots first; l = 1/3; u22 = 2 - (1/3)*4.
+    LU, perm, ok = orc.gepp(np.array([[1.0, 2.0], [3.0, 4.0]]))
+    assert ok and list(perm) == [1, 0]
+    assert LU[0, 0] == 3.0 and LU[0, 1] == 4.0
+    assert LU[1, 0] == 1.0 / 3.0
+    # fused multiply-add: one rounding of the exact value 2 - fl(1/3)*4
+    exact = Fraction(2) - Fraction(1.0 / 3.0) * 4
+    assert LU[1, 1] == float(exact)
+
+
+def test_gepp_pivot_ties_go_to_smallest_row(orc):
+    LU, perm, ok = orc.gepp(np.array([[2.0, 1.0], [-2.0, 5.0]]))
+    assert ok and list(perm) == [0, 1]  # |2| == |-2|: the first stays
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 17, 64])
+def test_gepp_reconstructs_and_bounds_multipliers(orc, r):
+    G = rand(r, r, 100 + r)
+    LU, perm, ok = orc.gepp(G)
+    assert ok
+    L = np.tril(LU, -1) + np.eye(r)
+    U = np.triu(LU)
+    assert np.abs(L).max() <= 1.0  # partial pivoting bounds the multipliers
+    np.testing.assert_allclose(L @ U, G[perm], rtol=0, atol=64 * r * EPS * np.abs(G).max())
+
+
+@pytest.mark.parametrize("r", [1, 3, 16, 64, 128])
+def test_inverse_matches_lapack(orc, r):
+    G = rand(r, r, 200 + r)
+    X = orc.inverse(G)
+    ref = np.linalg.inv(G)
+    tol = 16 * r * EPS * np.linalg.cond(G) * np.abs(ref).max()
+    np.testing.assert_allclose(X, ref, rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("r", [1, 4, 32, 200])
+def test_volume_matches_slogdet(orc, r):
+    G = 1e-3 * rand(r, r, 300 + r)  # det underflows for r=200; the log does not
+    _, _, lv = orc.volume(G)
+    sign, ref = np.linalg.slogdet(G)
+    assert sign != 0
+    assert abs(lv - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_singular_gepp_detected(orc):
+    G = rand(5, 5, 7)
+    G[:, 2] = 0.0
+    _, _, ok = orc.gepp(G)
+    assert not ok
+
+
+@pytest.mark.parametrize("rank", [2, 4])
+def test_pinv_matches_lapack(orc, rank):
+    X = rand(6, rank, 11) @ rand(rank, 6, 12)
+    P = orc.pinv(X)
+    np.testing.assert_allclose(P, np.linalg.pinv(X, rcond=6 * EPS), rtol=0, atol=1e-9 * np.abs(P).max())
+
+
+def test_pinv_of_nonsingular_is_inverse(orc):
+    G = rand(7, 7, 13)
+    np.testing.assert_allclose(orc.pinv(G), np.linalg.inv(G), rtol=0, atol=1e-11 * np.abs(np.linalg.inv(G)).max())
+
+
+# ---------------------------------------------------------------- ACA (Alg. 1)
+@pytest.mark.parametrize("shape", [(9, 13), (64, 8), (3, 50)])
+def test_aca_first_pivot_is_global_argmax(orc, shape):
+    A = rand(*shape, 21)
+    I, J, piv = orc.aca(A, 1)
+    i, j = np.unravel_index(np.argmax(np.abs(A)), A.shape)
+    assert (I[0], J[0]) == (i, j) and piv[0] == A[i, j]
+
+
+def test_aca_second_pivot_is_schur_complement_argmax(orc):
+    A = rand(12, 10, 22)
+    I, J, piv = orc.aca(A, 2)
+    i0, j0 = I[0], J[0]
+    S = A - np.outer(A[:, j0], A[i0, :]) / A[i0, j0]
+    S[i0, :] = 0.0
+    S[:, j0] = 0.0
+    i1, j1 = np.unravel_index(np.argmax(np.abs(S)), S.shape)
+    assert (I[1], J[1]) == (i1, j1)
+    assert abs(piv[1] - S[i1, j1]) <= 1e-14 * abs(S[i1, j1])
+
+
+@pytest.mark.parametrize("r", [1, 3, 8, 20])
+def test_aca_gecp_determinant_identity(orc, r):
+    # Complete-pivoting elimination: |det A(I,J)| is the product of the pivots.
+    A = rand(40, 30, 23 + r)
+    I, J, piv = orc.aca(A, r)
+    assert len(I) == r
+    _, ref = np.linalg.slogdet(A[np.ix_(I, J)])
+    assert abs(np.sum(np.log(np.abs(piv))) - ref) <= 1e-11 * r
+
+
+def test_aca_stops_at_exact_rank(orc):
+    A = rand(30, 4, 24) @ rand(4, 25, 25)
+    I, J, piv = orc.aca(A, 8)
+    assert len(I) == 4  # fifth pivot is rounding noise below theta
+
+
+# ---------------------------------------------------------------- Sherman-Morrison swaps
+def test_row_swap_equals_fresh_interpolation(orc):
+    A = rand(50, 6, 31)
+    I = np.array([3, 10, 17, 22, 40, 45])
+    B = row_interp(A, I, np.arange(6))
+    i_star, k_star = 7, 2
+    B2 = orc.sm_row_update(B, i_star, k_star)
+    I2 = I.copy()
+    I2[k_star] = i_star
+    ref = row_interp(A, I2, np.arange(6))
+    np.testing.assert_allclose(B2, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # determinant ratio of the swap is B(i*,k*) (Cramer's rule)
+    ratio = np.linalg.det(A[I2]) / np.linalg.det(A[I])
+    assert abs(ratio - B[i_star, k_star]) <= 1e-12 * abs(ratio)
+
+
+def test_col_swap_equals_fresh_interpolation(orc):
+    A = rand(6, 40, 32)
+    I = np.arange(6)
+    Jc = np.arange(40)
+    J = np.array([1, 5, 9, 20, 30, 39])
+    Bc = col_interp(A, I, J, Jc)
+    c_star, k_star = 12, 4
+    Bc2 = orc.sm_col_update(Bc, k_star, c_star)
+    J2 = J.copy()
+    J2[k_star] = c_star
+    ref = col_interp(A, I, J2, Jc)
+    np.testing.assert_allclose(Bc2, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_swap_loop_reaches_dominance_and_grows_volume(orc):
+    A = rand(120, 40, 33)
+    r = 6
+    I0 = np.arange(r) * 3
+    J0 = np.arange(r) * 2
+    I, J, st = orc.swap_loop(A, I0, J0, np.arange(40))
+    assert st["status"] == 0 and st["swaps"] > 0
+    assert np.abs(row_interp(A, I, J)).max() <= 1 + 1e-12
+    assert np.abs(col_interp(A, I, J, np.arange(40))).max() <= 1 + 1e-12
+    assert orc.logvol(A, I, J) > orc.logvol(A, I0, J0)
+
+
+def test_swap_cap_reports_noconv(orc):
+    A = rand(120, 40, 33)
+    I, J, st = orc.swap_loop(A, np.arange(6) * 3, np.arange(6) * 2, np.arange(40), smax=1)
+    assert st["status"] == orc.WARN_NOCONV and st["swaps"] == 1
+
+
+# ---------------------------------------------------------------- whole selection
+@pytest.mark.parametrize("shape,w", [((37, 200), 16), ((100, 64), 0), ((5, 300), 7), ((300, 9), 2)])
+def test_select_rank_one_is_global_argmax(orc, shape, w):
+    A = rand(*shape, 41)
+    res = orc.select(A, 1, w=w)
+    i, j = np.unravel_index(np.argmax(np.abs(A)), A.shape)
+    assert res["status"] == 0 and (res["I"][0], res["J"][0]) == (i, j)
+
+
+def _read_golden():
+    ents, cases, m, n = [], [], 0, 0
+    with open(os.path.join(GOLDEN, "diag_closed_form.txt")) as f:
+        for line in f:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "m":
+                m = int(t[1])
+            elif t[0] == "n":
+                n = int(t[1])
+            elif t[0] == "entry":
+                ents.append((int(t[1]), int(t[2]), float(t[3])))
+            elif t[0] == "case":
+                d = {"name": t[1]}
+                k = 2
+                while k < len(t):
+                    key = t[k]
+                    if key in ("I", "J"):
+                        d[key] = [int(x) for x in t[k + 1:k + 4]]
+                        k += 4
+                    else:
+                        d[key] = float(t[k + 1])
+                        k += 2
+                cases.append(d)
+    A = np.zeros((m, n))
+    for i, j, v in ents:
+        A[i, j] = v
+    return A, cases
+
+
+@pytest.mark.parametrize("case", ["single", "two_blocks"])
+def test_golden_permuted_diagonal(orc, case):
+    A, cases = _read_golden()
+    c = next(c for c in cases if c["name"] == case)
+    r = int(c["r"])
+    res = orc.select(A, r, w=int(c["w"]))
+    assert res["status"] == 0
+    assert list(res["I"]) == c["I"] and list(res["J"]) == c["J"]
+    C, U, R, used = orc.assemble(A, res["I"], res["J"])
+    cheb, fro = orc.residual(A, C, U, R)
+    assert cheb == c["cheb"]
+    assert abs(fro * fro - c["fro2"]) < 1e-15
+    if case == "single":
+        assert np.array_equal(U, np.array([[0, 0, 1 / 3], [-1 / 4, 0, 0], [0, 1 / 5, 0]]))
+
+
+def test_golden_tie_rule(orc):
+    A = np.array([[1.0, -3.0], [3.0, 2.0]])
+    res = orc.select(A, 1)
+    assert (res["I"][0], res["J"][0]) == (0, 1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_bruteforce_theorems_and_method(orc, seed, r):
+    # Thm 1 and Thm 2 at the exact maximal-volume cross (found by enumeration),
+    # evaluated through the oracle's assembly and residual.
+    A = rand(8, 7, 500 + seed) @ np.diag(0.5 ** np.arange(7)) @ rand(7, 7, 600 + seed)
+    Ib, Jb, vmax = brute_force_maxvol(A, r)
+    C, U, R, _ = orc.assemble(A, Ib, Jb)
+    cheb, fro = orc.residual(A, C, U, R)
+    s = np.linalg.svd(A, compute_uv=False)
+    thm1 = (r + 1) * s[r]
+    thm2 = thm1 / np.sqrt(1.0 + np.sum(s[r] ** 2 / s[:r] ** 2))
+    assert cheb <= thm1 * (1 + 1e-12)
+    assert cheb <= thm2 * (1 + 1e-12)
+    # The method (two column blocks) never beats the exhaustive optimum, and its
+    # output admits no single improving row swap nor column swap among the
+    # root's candidates (dominance, checked by brute-force determinants).
+    res = orc.select(A, r, w=max(r, 3), trace=True)
+    assert res["status"] == 0
+    vol = abs(np.linalg.det(A[np.ix_(res["I"], res["J"])]))
+    assert vol <= vmax * (1 + 1e-12)
+    Jc = root_candidates(res["trace"], r)
+    assert single_swap_gain(A, res["I"], res["J"], Jc) <= 1 + 1e-10
+
+
+def test_dominance_and_interpolation_c1(orc):
+    A = W.c1(1).numpy()
+    r = 16
+    res = orc.select(A, r, trace=True)
+    assert res["status"] == 0
+    I, J = res["I"], res["J"]
+    amax = np.abs(A).max()
+    assert np.abs(row_interp(A, I, J)).max() <= 1 + 1e-12
+    assert np.abs(col_interp(A, I, J, root_candidates(res["trace"], r))).max() <= 1 + 1e-12
+    C, U, R, used = orc.assemble(A, I, J)
+    assert not used
+    E = A - C @ U @ R
+    assert np.abs(E[I, :]).max() <= 1e3 * r * EPS * amax
+    assert np.abs(E[:, J]).max() <= 1e3 * r * EPS * amax
+    cheb, fro = orc.residual(A, C, U, R)
+    assert abs(cheb - np.abs(E).max()) <= 1e-10 * amax
+    # spectrum is known in closed form: sigma_17 = 1e-8; observed error is far
+    # below the maximal-volume bound (r+1) sigma_{r+1} of Thm 1
+    assert cheb <= (r + 1) * 1e-8
+    # the tracked logvol is the fresh one
+    assert abs(res["logvol"] - orc.logvol(A, I, J)) <= 1e-12 * abs(res["logvol"])
+
+
+def test_tree_volume_is_monotone(orc):
+    A = W.c1(1).numpy()
+    res = orc.select(A, 16, trace=True)
+    tr = res["trace"]
+    meta = tr["meta"]
+    for lvl in range(1, meta[:, 0].max() + 1):
+        kids = np.where(meta[:, 0] == lvl - 1)[0]
+        for p in np.where(meta[:, 0] == lvl)[0]:
+            idx = meta[p, 1]
+            ch = [kids[2 * idx]] + ([kids[2 * idx + 1]] if 2 * idx + 1 < len(kids) else [])
+            best = max(trace_logvol(tr, k) for k in ch)
+            assert trace_logvol(tr, p) >= best - 1e-12
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_exact_rank_input_is_reproduced(orc, seed):
+    m, n, r = 90, 130, 7
+    A = rand(m, r, seed) @ rand(r, n, seed + 50)
+    res = orc.select(A, r, w=16)
+    assert res["status"] == 0
+    C, U, R, _ = orc.assemble(A, res["I"], res["J"])
+    cheb, _ = orc.residual(A, C, U, R)
+    assert cheb <= 1e3 * r * EPS * np.abs(A).max()
+
+
+def test_full_rank_cross_reproduces(orc):
+    A = rand(12, 12, 3)
+    res = orc.select(A, 12, w=12)
+    C, U, R, _ = orc.assemble(A, res["I"], res["J"])
+    cheb, _ = orc.residual(A, C, U, R)
+    assert cheb <= 1e4 * 12 * EPS * np.abs(A).max()
+
+
+# ---------------------------------------------------------------- metamorphic relations
+def test_row_permutation_equivariance(orc):
+    A = rand(150, 96, 61)
+    base = orc.select(A, 5, w=16)
+    p = np.random.default_rng(62).permutation(150)
+    res = orc.select(A[p], 5, w=16)
+    assert np.array_equal(np.sort(p[res["I"]]), base["I"])
+    assert np.array_equal(res["J"], base["J"])
+    assert (res["swaps"], res["phases"], res["refreshes"]) == (base["swaps"], base["phases"], base["refreshes"])
+
+
+@pytest.mark.parametrize("scale", [2.0 ** 40, 2.0 ** -300, -1.0, -(2.0 ** 7)])
+def test_power_of_two_scaling_and_negation(orc, scale):
+    A = rand(80, 70, 63)
+    base = orc.select(A, 6, w=8)
+    res = orc.select(scale * A, 6, w=8)
+    assert np.array_equal(res["I"], base["I"]) and np.array_equal(res["J"], base["J"])
+    C0, U0, R0, _ = orc.assemble(A, base["I"], base["J"])
+    C1, U1, R1, _ = orc.assemble(scale * A, res["I"], res["J"])
+    assert np.array_equal(U1, U0 / scale)
+    c0, _ = orc.residual(A, C0, U0, R0)
+    c1, _ = orc.residual(scale * A, C1, U1, R1)
+    assert c1 == abs(scale) * c0
+
+
+# ---------------------------------------------------------------- paper test matrices
+def test_hilbert_rank_one_and_dominance(orc):
+    A = W.hilbert(256)
+    res = orc.select(A, 1)
+    assert (res["I"][0], res["J"][0]) == (0, 0)  # H(1,1) = 1 is the largest entry
+    res = orc.select(A, 6)
+    assert res["status"] == 0
+    assert np.abs(row_interp(A, res["I"], res["J"])).max() <= 1 + 1e-9
+
+
+def test_recip_lowrank_rank_short_matches_spectrum(orc):
+    # H = A B with 1/(i+j) factors (Sec. 3.1): Cauchy factors make the singular
+    # values of H fall off geometrically, so the pivots of the method drop below
+    # theta = max(m,n) 2^-52 ||H||_C exactly where the spectrum does (the gap
+    # between consecutive singular values there is > 100x).
+    A = W.recip_lowrank(256, 20)
+    s = np.linalg.svd(A, compute_uv=False)
+    theta = 256 * EPS * np.abs(A).max()
+    res = orc.select(A, 20)
+    assert res["status"] == orc.ERR_RANK
+    assert res["rank"] == int(np.sum(s > theta))
+    # well inside the numerical rank the cross error sits below the Thm 1 bound
+    r = 5
+    res = orc.select(A, r)
+    assert res["status"] == 0
+    C, U, R, _ = orc.assemble(A, res["I"], res["J"])
+    cheb, _ = orc.residual(A, C, U, R)
+    assert cheb <= (r + 1) * s[r]
+
+
+# ---------------------------------------------------------------- error conventions
+@pytest.mark.parametrize("r,w,tau,ms", [(0, 0, 0.0, 0), (11, 0, 0.0, 0), (4, 3, 0.0, 0),
+                                        (2, -1, 0.0, 0), (2, 0, -1.0, 0), (2, 0, 0.0, -5)])
+def test_argument_errors(orc, r, w, tau, ms):
+    rc, _, _, _ = orc.select_raw(rand(10, 12, 1), r, w, tau, ms)
+    assert rc == orc.ERR_ARG
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_input(orc, bad):
+    A = rand(20, 20, 2)
+    A[7, 3] = bad
+    rc, _, _, _ = orc.select_raw(A, 3)
+    assert rc == orc.ERR_NONFINITE
+
+
+def test_zero_matrix_is_rank_zero(orc):
+    rc, info, _, _ = orc.select_raw(np.zeros((9, 9)), 2)
+    assert rc == orc.ERR_RANK and info.rank == 0
+
+
+def test_rank_deficient_reports_pivots_found(orc):
+    A = rand(40, 2, 3) @ rand(2, 64, 4)
+    rc, info, I, J = orc.select_raw(A, 4, w=16)
+    assert rc == orc.ERR_RANK and info.rank == 2
+    assert np.all(I[:2] >= 0) and np.all(I[2:] == -1)
