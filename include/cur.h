@@ -1,0 +1,172 @@
+/*
+ * cur.h -- C ABI of libcur: maximal-volume CUR selection, assembly and
+ * residual on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2502.11017, "Scalable Binary CUR Low-Rank Approximation"):
+ *   A (m x n) ~ C U R with C = A(:,J), U = A(I,J)^+, R = A(I,:)      (Sec. 1.1)
+ *   I, J chosen so that |det A(I,J)| is near maximal                (Def. 1, Sec. 1.2)
+ *   residual measured in the Chebyshev norm max|A - CUR|             (Thm 1, Thm 2)
+ *   and as the Frobenius relative error ||A - CUR||_F / ||A||_F      (Sec. 3.1)
+ * Selection: the columns are split into contiguous blocks (Alg. 3 block
+ * partition); each block is started by adaptive cross approximation with
+ * complete pivoting (Alg. 1) and refined by maxvol row/column swaps (the
+ * maximal-volume search cited in Sec. 1.2); blocks are merged pairwise up a
+ * binary tree, each merge re-running the swaps over the union of the
+ * children's columns.
+ *
+ * Conventions common to every entry point
+ *   - Matrices are row-major with a leading dimension counted in elements.
+ *   - Every matrix and index pointer is a DEVICE pointer owned by the caller;
+ *     the library never frees or retains it.  Outputs written by the library
+ *     must not alias inputs.
+ *   - Indices are 0-based int64 and are returned sorted ascending.
+ *   - Argument errors (sizes, null pointers, bad options) are detected on the
+ *     host before any device work and return CUR_ERR_ARG; a description of
+ *     the last error of the calling thread is available from
+ *     cur_last_error().
+ *   - Data-dependent outcomes (non-finite input, rank shortfall, swap budget
+ *     exhausted) are computed on the device; the calls are synchronous with
+ *     respect to the context's stream and return them.
+ *   - A context must not be used from two host threads at once.
+ */
+#ifndef CUR_H
+#define CUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cur_ctx_s* cur_ctx;
+
+typedef enum {
+  CUR_OK = 0,
+  CUR_WARN_NOCONV = 1,    /* result valid; some node spent its swap budget, dominance not certified */
+  CUR_ERR_ARG = -1,       /* invalid argument (host-side check)                                     */
+  CUR_ERR_RANK = -2,      /* fewer than r pivots above the numerical-zero threshold                  */
+  CUR_ERR_NONFINITE = -3, /* A holds NaN or Inf                                                      */
+  CUR_ERR_DEVICE = -4,    /* a HIP call failed                                                       */
+  CUR_ERR_NOMEM = -5,     /* device workspace allocation failed                                      */
+  CUR_ERR_INTERNAL = -6   /* a cross that must be nonsingular was found singular                     */
+} cur_status;
+
+typedef enum { CUR_F64 = 0, CUR_F32 = 1 } cur_dtype;
+
+/* Arithmetic of the residual GEMM E = A - (C U) R (cur_residual). */
+typedef enum {
+  CUR_PREC_NATIVE = 0, /* in the input dtype (FP64 or FP32)                                  */
+  CUR_PREC_BF16X3 = 1, /* three BF16 products (hi*hi + hi*lo + lo*hi), FP32 accumulation    */
+  CUR_PREC_FP8 = 2     /* two-term e4m3 split with per-tile scales, FP32 accumulation        */
+} cur_prec;
+
+/* Per-node record of the selection tree (optional, for inspection and tests).
+ * Nodes are listed level by level (leaves first), index ascending; an odd
+ * last node of a level is promoted to the next level unchanged. */
+typedef struct {
+  int32_t capacity;  /* number of records the arrays below can hold               */
+  int32_t count;     /* written: number of records                                */
+  int64_t* meta;     /* host, capacity x 10: level, index, q, short, promoted,
+                        nocap, swaps, phases, refreshes, volume exponent          */
+  double* vol_mant;  /* host, capacity: volume mantissa in [0.5,1) (0 if short)   */
+  int64_t* I;        /* host, capacity x r (unused entries -1)                    */
+  int64_t* J;        /* host, capacity x r                                        */
+} cur_trace;
+
+typedef struct {
+  int32_t struct_size; /* sizeof(cur_opts), for ABI versioning                                   */
+  int32_t col_block;   /* leaf column-block width w; 0 -> max(64, r); must be >= r               */
+  double tau;          /* a swap happens iff |B| > 1 + tau; 0 -> 1e-13 (F64) / 1e-4 (F32)        */
+  int32_t max_swaps;   /* swap budget per tree node; 0 -> 64 r                                   */
+  int32_t prec;        /* cur_prec of the assembly/residual GEMMs (selection itself is exact)    */
+  int32_t propose;     /* 0: no candidate proposal                                               */
+  int32_t reserved0;
+  const void* mlp;     /* reserved (must be NULL when propose == 0)                              */
+  uint64_t seed;       /* reserved                                                               */
+  cur_trace* trace;    /* host pointer or NULL: per-node tree records                            */
+} cur_opts;
+
+typedef struct {
+  int32_t rank;      /* r, or the number q < r of pivots found (CUR_ERR_RANK)  */
+  int32_t nodes;     /* leaves + merges processed                             */
+  int32_t phases;    /* swap phases over all nodes                            */
+  int32_t refreshes; /* fresh interpolation-matrix computations              */
+  int64_t swaps;     /* row + column swaps over all nodes                     */
+  double logvol;     /* log|det A(I,J)| of the result (fresh LU)              */
+} cur_info;
+
+/* Fill *opts with the defaults (struct_size set, everything else zero). */
+void cur_opts_init(cur_opts* opts);
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is
+ * used for all work; NULL creates and owns a stream of the default priority.
+ * The context owns a device workspace that grows on demand. */
+cur_status cur_create(cur_ctx* out, int device, void* hip_stream);
+cur_status cur_destroy(cur_ctx ctx);
+const char* cur_strerror(cur_status s);
+/* Description of the last error returned to the calling thread ("" if none). */
+const char* cur_last_error(void);
+
+/*
+ * Selection (Def. 1 objective, Alg. 1 leaf start, Alg. 3 block partition,
+ * binary merge tree).
+ *   A      device, m x n, row-major, leading dimension lda >= n, dtype `dtype`
+ *   r      1 <= r <= min(m, n)
+ *   opts   NULL for defaults
+ *   I, J   device int64[r]: selected rows and columns, ascending.  On
+ *          CUR_ERR_RANK the first info->rank entries hold the pivots found and
+ *          the rest are -1.
+ *   info   host, nullable
+ * The FP64 path computes exactly the sequence of decisions of the documented
+ * algorithm (bit-identical arithmetic in every decision-relevant quantity).
+ * The FP32 path streams the interpolation matrices in FP32 (fresh ones are
+ * computed in FP64 from the FP32 input) with tau = 1e-4 by default.
+ */
+cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                      int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info);
+
+/*
+ * Assembly (Sec. 1.1): C = A(:,J) (m x r, ld r, dtype), R = A(I,:) (r x n,
+ * ld n, dtype), U = A(I,J)^+ (r x r, ld r, FP64).  U is the inverse from LU
+ * with partial pivoting, or, when a pivot is zero or min|u_kk|/max|u_kk| <
+ * r 2^-52, the pseudo-inverse from a one-sided Jacobi SVD with singular values
+ * below r 2^-52 sigma_max dropped.  I, J: device int64[r], each in range.
+ */
+cur_status cur_assemble(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                        int32_t r, const int64_t* I, const int64_t* J, void* C, double* U, void* R);
+
+/*
+ * Residual (Thm 1 Chebyshev norm, Sec. 3.1 Frobenius error) of the factors of
+ * cur_assemble: E = A - (C U) R, never stored.
+ *   cheb     host: max |E(i,j)|
+ *   fro_rel  host, nullable: ||E||_F / ||A||_F
+ *   prec     cur_prec of the GEMM (NATIVE for FP64 input; NATIVE, BF16X3 or
+ *            FP8 for FP32 input).  U is always FP64; C U is formed in FP64.
+ */
+cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                        int32_t r, const void* C, const double* U, const void* R, int32_t prec,
+                        double* cheb, double* fro_rel);
+
+/* One independent selection of a batch. */
+typedef struct {
+  int32_t dtype; /* cur_dtype                        */
+  int32_t r;
+  const void* A; /* device                           */
+  int64_t m, n, lda;
+  int64_t* I;    /* device int64[r]                  */
+  int64_t* J;    /* device int64[r]                  */
+} cur_item;
+
+/*
+ * Batched selection of `count` independent matrices of any shapes and ranks
+ * (same rules as cur_select for each item).  per_item: host cur_status[count]
+ * (nullable); the return value is the worst status (errors before warnings).
+ * opts->trace must be NULL.
+ */
+cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items, const cur_opts* opts,
+                              cur_status* per_item);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUR_H */

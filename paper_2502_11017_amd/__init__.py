@@ -1,0 +1,261 @@
+"""Python binding of libcur (maximal-volume CUR selection on MI355X).
+
+Argument marshalling only: every step of the selection, assembly and residual
+runs in the HIP library ``libcur.so`` built from ``csrc/``.  torch provides
+device memory and the current HIP stream; no torch operator runs on the path.
+Importing works without a GPU (the library loads, its symbols resolve);
+calling a compute function without the built library or without a GPU raises.
+
+Functions mirror the C ABI of ``include/cur.h``:
+  select(A, r, ...)            -> dict(I, J, status, rank, nodes, phases, refreshes, swaps, logvol)
+  assemble(A, I, J)            -> (C, U, R)
+  residual(A, C, U, R, prec)   -> (cheb, fro_rel)
+  select_batched(As, rs, ...)  -> list of (I, J, status)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcur.so")
+
+OK, WARN_NOCONV = 0, 1
+ERR_ARG, ERR_RANK, ERR_NONFINITE, ERR_DEVICE, ERR_NOMEM, ERR_INTERNAL = -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+PREC_NATIVE, PREC_BF16X3, PREC_FP8 = 0, 1, 2
+TRACE_FIELDS = ("level", "index", "q", "short", "promoted", "nocap", "swaps", "phases",
+                "refreshes", "vol_e")
+
+EXPORTS = ("cur_opts_init", "cur_create", "cur_destroy", "cur_strerror", "cur_last_error",
+           "cur_select", "cur_assemble", "cur_residual", "cur_select_batched")
+
+
+class CurError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("meta", ctypes.c_void_p), ("vol_mant", ctypes.c_void_p),
+                ("I", ctypes.c_void_p), ("J", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("col_block", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("max_swaps", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("propose", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("mlp", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("trace", ctypes.POINTER(Trace))]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("nodes", ctypes.c_int32), ("phases", ctypes.c_int32),
+                ("refreshes", ctypes.c_int32), ("swaps", ctypes.c_int64), ("logvol", ctypes.c_double)]
+
+
+class Item(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("r", ctypes.c_int32), ("A", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("I", ctypes.c_void_p), ("J", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcur.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2502_11017_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.cur_opts_init.argtypes = [ctypes.POINTER(Opts)]
+        L.cur_opts_init.restype = None
+        L.cur_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+        L.cur_create.restype = ctypes.c_int
+        L.cur_destroy.argtypes = [P]
+        L.cur_destroy.restype = ctypes.c_int
+        L.cur_strerror.argtypes = [ctypes.c_int]
+        L.cur_strerror.restype = ctypes.c_char_p
+        L.cur_last_error.argtypes = []
+        L.cur_last_error.restype = ctypes.c_char_p
+        L.cur_select.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, ctypes.POINTER(Opts), P, P,
+                                 ctypes.POINTER(Info)]
+        L.cur_select.restype = ctypes.c_int
+        L.cur_assemble.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, P, P]
+        L.cur_assemble.restype = ctypes.c_int
+        L.cur_residual.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, i32,
+                                   ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.cur_residual.restype = ctypes.c_int
+        L.cur_select_batched.argtypes = [P, i32, ctypes.POINTER(Item), ctypes.POINTER(Opts),
+                                         ctypes.POINTER(ctypes.c_int)]
+        L.cur_select_batched.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().cur_last_error().decode()
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise CurError(rc, f"{lib().cur_strerror(rc).decode()}: {last_error()}")
+    return rc
+
+
+_ctx = {}
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def context(device=None):
+    """Per-(device, stream) library context, created on first use."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("libcur needs a HIP GPU; none is visible")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    if key not in _ctx:
+        c = ctypes.c_void_p()
+        _check(lib().cur_create(ctypes.byref(c), dev, ctypes.c_void_p(stream)))
+        _ctx[key] = c
+    return _ctx[key]
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("A must be float64 or float32")
+
+
+def _matrix(A):
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor (unit column stride)")
+    if not A.is_cuda:
+        raise ValueError("A must live on the GPU")
+    return A.shape[0], A.shape[1], A.stride(0)
+
+
+def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None) -> Opts:
+    o = Opts()
+    lib().cur_opts_init(ctypes.byref(o))
+    o.col_block = int(col_block)
+    o.tau = float(tau)
+    o.max_swaps = int(max_swaps)
+    o.prec = int(prec)
+    if trace is not None:
+        o.trace = ctypes.pointer(trace)
+    return o
+
+
+def tree_size(n: int, w: int) -> int:
+    c = max(1, n // w)
+    tot = 0
+    while True:
+        tot += c
+        if c <= 1:
+            return tot
+        c = (c + 1) // 2
+
+
+def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, trace: bool = False,
+           allow=(OK, WARN_NOCONV, ERR_RANK)):
+    """Select r rows I and r columns J of the device matrix A (cur_select)."""
+    torch = _torch()
+    m, n, lda = _matrix(A)
+    ctx = context(A.device.index)
+    I = torch.empty(r, dtype=torch.int64, device=A.device)
+    J = torch.empty(r, dtype=torch.int64, device=A.device)
+    info = Info()
+    tr = None
+    host = None
+    if trace:
+        import numpy as np
+
+        w = col_block if col_block else max(64, r)
+        N = tree_size(n, max(w, 1))
+        host = {"meta": np.zeros((N, 10), dtype=np.int64), "vol_m": np.zeros(N),
+                "I": np.zeros((N, r), dtype=np.int64), "J": np.zeros((N, r), dtype=np.int64)}
+        tr = Trace(N, 0, host["meta"].ctypes.data, host["vol_m"].ctypes.data,
+                   host["I"].ctypes.data, host["J"].ctypes.data)
+    o = make_opts(col_block, tau, max_swaps, trace=tr)
+    rc = lib().cur_select(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
+                          ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                          ctypes.byref(info))
+    _check(rc, allow)
+    out = {"I": I, "J": J, "status": rc, "rank": info.rank, "nodes": info.nodes,
+           "phases": info.phases, "refreshes": info.refreshes, "swaps": info.swaps,
+           "logvol": info.logvol}
+    if trace:
+        out["trace"] = host
+    return out
+
+
+def assemble(A, I, J):
+    """C = A(:,J), U = A(I,J)^+ (FP64), R = A(I,:) (cur_assemble)."""
+    torch = _torch()
+    m, n, lda = _matrix(A)
+    r = int(I.numel())
+    ctx = context(A.device.index)
+    C = torch.empty((m, r), dtype=A.dtype, device=A.device)
+    U = torch.empty((r, r), dtype=torch.float64, device=A.device)
+    R = torch.empty((r, n), dtype=A.dtype, device=A.device)
+    I = I.to(torch.int64).contiguous()
+    J = J.to(torch.int64).contiguous()
+    rc = lib().cur_assemble(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
+                            ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                            ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                            ctypes.c_void_p(R.data_ptr()))
+    _check(rc)
+    return C, U, R
+
+
+def residual(A, C, U, R, prec: int = PREC_NATIVE):
+    """(max|A - CUR|, ||A - CUR||_F / ||A||_F) (cur_residual)."""
+    m, n, lda = _matrix(A)
+    r = int(U.shape[0])
+    ctx = context(A.device.index)
+    C = C.contiguous()
+    U = U.contiguous()
+    R = R.contiguous()
+    cheb = ctypes.c_double()
+    fro = ctypes.c_double()
+    rc = lib().cur_residual(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
+                            ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                            ctypes.c_void_p(R.data_ptr()), int(prec), ctypes.byref(cheb), ctypes.byref(fro))
+    _check(rc)
+    return cheb.value, fro.value
+
+
+def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0):
+    """Independent selections of several device matrices (cur_select_batched)."""
+    torch = _torch()
+    cnt = len(As)
+    items = (Item * max(cnt, 1))()
+    outs = []
+    for k, (A, r) in enumerate(zip(As, rs)):
+        m, n, lda = _matrix(A)
+        I = torch.empty(r, dtype=torch.int64, device=A.device)
+        J = torch.empty(r, dtype=torch.int64, device=A.device)
+        items[k] = Item(_dtype_code(A), int(r), A.data_ptr(), m, n, lda, I.data_ptr(), J.data_ptr())
+        outs.append((I, J))
+    per = (ctypes.c_int * max(cnt, 1))()
+    o = make_opts(col_block, tau, max_swaps)
+    ctx = context(As[0].device.index if cnt else None)
+    rc = lib().cur_select_batched(ctx, cnt, items, ctypes.byref(o), per)
+    _check(rc, (OK, WARN_NOCONV, ERR_RANK))
+    return [(I, J, per[k]) for k, (I, J) in enumerate(outs)], rc

@@ -1,0 +1,254 @@
+// C ABI front end: argument validation (host, before any device work),
+// context and workspace management, error strings.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cur_internal.hpp"
+
+namespace cur {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+cur_status ensure_arena(cur_ctx ctx, size_t bytes) {
+  if (ctx->arena_bytes >= bytes) return CUR_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) {
+    set_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+    return CUR_ERR_DEVICE;
+  }
+  if (ctx->arena) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->arena);
+    ctx->arena = nullptr;
+    ctx->arena_bytes = 0;
+  }
+  size_t want = bytes + bytes / 8 + (1 << 20);
+  e = hipMalloc(&ctx->arena, want);
+  if (e != hipSuccess) {
+    ctx->arena = nullptr;
+    set_error("device workspace of " + std::to_string(want) + " bytes: " + hipGetErrorString(e));
+    return CUR_ERR_NOMEM;
+  }
+  ctx->arena_bytes = want;
+  return CUR_OK;
+}
+
+static cur_status arg_error(const std::string& msg) {
+  set_error(msg);
+  return CUR_ERR_ARG;
+}
+
+static cur_status check_matrix(cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r) {
+  if (dtype != CUR_F64 && dtype != CUR_F32) return arg_error("dtype must be CUR_F64 or CUR_F32");
+  if (!A) return arg_error("A is NULL");
+  if (m < 1 || n < 1) return arg_error("m and n must be >= 1");
+  if (lda < n) return arg_error("lda must be >= n");
+  if (r < 1 || (int64_t)r > m || (int64_t)r > n) return arg_error("r must satisfy 1 <= r <= min(m, n)");
+  if (r > 128) return arg_error("r > 128 is not supported by this build");
+  if (m > ((int64_t)1 << 40) || n > ((int64_t)1 << 40)) return arg_error("matrix dimensions too large");
+  return CUR_OK;
+}
+
+// Resolve the options (defaults filled in) or report an argument error.
+static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, int64_t n, cur_opts* out) {
+  cur_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.struct_size = sizeof(cur_opts);
+  if (in) {
+    if (in->struct_size != (int32_t)sizeof(cur_opts)) return arg_error("cur_opts.struct_size mismatch");
+    o = *in;
+  }
+  if (o.col_block < 0) return arg_error("col_block must be >= 0");
+  if (o.col_block == 0) o.col_block = r > 64 ? r : 64;
+  if (o.col_block < r) return arg_error("col_block must be >= r");
+  if (!(o.tau >= 0.0)) return arg_error("tau must be >= 0");
+  if (o.tau == 0.0) o.tau = dtype == CUR_F64 ? 1e-13 : 1e-4;
+  if (o.max_swaps < 0) return arg_error("max_swaps must be >= 0");
+  if (o.max_swaps == 0) o.max_swaps = 64 * r;
+  if (o.prec < CUR_PREC_NATIVE || o.prec > CUR_PREC_FP8) return arg_error("prec out of range");
+  if (o.propose != 0) return arg_error("propose must be 0 in this build");
+  if (o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
+  if (o.trace) {
+    int64_t b = n / o.col_block;
+    if (b < 1) b = 1;
+    int64_t tot = 0;
+    for (int64_t c = b;;) {
+      tot += c;
+      if (c <= 1) break;
+      c = (c + 1) / 2;
+    }
+    if (!o.trace->meta || !o.trace->vol_mant || !o.trace->I || !o.trace->J)
+      return arg_error("cur_trace arrays must be non-NULL");
+    if (o.trace->capacity < tot) return arg_error("cur_trace.capacity too small for the tree");
+  }
+  (void)n;
+  *out = o;
+  return CUR_OK;
+}
+
+}  // namespace cur
+
+using namespace cur;
+
+extern "C" {
+
+void cur_opts_init(cur_opts* opts) {
+  if (!opts) return;
+  std::memset(opts, 0, sizeof(*opts));
+  opts->struct_size = sizeof(cur_opts);
+}
+
+const char* cur_strerror(cur_status s) {
+  switch (s) {
+    case CUR_OK: return "ok";
+    case CUR_WARN_NOCONV: return "swap budget exhausted; dominance not certified";
+    case CUR_ERR_ARG: return "invalid argument";
+    case CUR_ERR_RANK: return "matrix rank below r";
+    case CUR_ERR_NONFINITE: return "non-finite input";
+    case CUR_ERR_DEVICE: return "HIP device error";
+    case CUR_ERR_NOMEM: return "out of device memory";
+    case CUR_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* cur_last_error(void) { return last_error(); }
+
+cur_status cur_create(cur_ctx* out, int device, void* hip_stream) {
+  if (!out) return arg_error("out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    set_error(std::string("no HIP device: ") + (e == hipSuccess ? "count 0" : hipGetErrorString(e)));
+    return CUR_ERR_DEVICE;
+  }
+  if (device < 0 || device >= count) return arg_error("device index out of range");
+  CUR_HIP_CHECK(hipSetDevice(device));
+  cur_ctx c = new cur_ctx_s();
+  c->device = device;
+  c->arena = nullptr;
+  c->arena_bytes = 0;
+  c->last_pinv = 0;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      set_error(std::string("hipStreamCreate: ") + hipGetErrorString(e));
+      return CUR_ERR_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  e = hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    set_error(std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    return CUR_ERR_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+  else c->cu_count = 256;
+  *out = c;
+  return CUR_OK;
+}
+
+cur_status cur_destroy(cur_ctx ctx) {
+  if (!ctx) return arg_error("ctx is NULL");
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->arena) hipFree(ctx->arena);
+  if (ctx->host_flag) hipHostFree(ctx->host_flag);
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return CUR_OK;
+}
+
+cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                      int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info) {
+  cur_status st = check_matrix(dtype, A, m, n, lda, r);
+  if (st != CUR_OK) return st;
+  if (!I || !J) return arg_error("I and J must be non-NULL device pointers");
+  cur_opts o;
+  st = resolve_opts(opts, dtype, r, n, &o);
+  if (st != CUR_OK) return st;
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return select_dispatch(ctx, dtype, A, m, n, lda, r, o, I, J, info);
+}
+
+cur_status cur_assemble(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                        int32_t r, const int64_t* I, const int64_t* J, void* C, double* U, void* R) {
+  cur_status st = check_matrix(dtype, A, m, n, lda, r);
+  if (st != CUR_OK) return st;
+  if (!I || !J || !C || !U || !R) return arg_error("I, J, C, U and R must be non-NULL device pointers");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  // indices must be in range: checked on a host copy (r values each)
+  std::vector<int64_t> hI(r), hJ(r);
+  CUR_HIP_CHECK(hipMemcpyAsync(hI.data(), I, sizeof(int64_t) * r, hipMemcpyDeviceToHost, ctx->stream));
+  CUR_HIP_CHECK(hipMemcpyAsync(hJ.data(), J, sizeof(int64_t) * r, hipMemcpyDeviceToHost, ctx->stream));
+  CUR_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < r; ++k)
+    if (hI[k] < 0 || hI[k] >= m || hJ[k] < 0 || hJ[k] >= n) return arg_error("I or J entry out of range");
+  set_error("");
+  return assemble_dispatch(ctx, dtype, A, m, n, lda, r, I, J, C, U, R);
+}
+
+cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                        int32_t r, const void* C, const double* U, const void* R, int32_t prec,
+                        double* cheb, double* fro_rel) {
+  cur_status st = check_matrix(dtype, A, m, n, lda, r);
+  if (st != CUR_OK) return st;
+  if (!C || !U || !R) return arg_error("C, U and R must be non-NULL device pointers");
+  if (!cheb) return arg_error("cheb must be a non-NULL host pointer");
+  if (prec < CUR_PREC_NATIVE || prec > CUR_PREC_FP8) return arg_error("prec out of range");
+  if (dtype == CUR_F64 && prec != CUR_PREC_NATIVE) return arg_error("FP64 input takes CUR_PREC_NATIVE");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return residual_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
+}
+
+cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items, const cur_opts* opts,
+                              cur_status* per_item) {
+  if (count < 0) return arg_error("count must be >= 0");
+  if (count > 0 && !items) return arg_error("items is NULL");
+  if (opts && opts->trace) return arg_error("opts->trace must be NULL for batched selection");
+  for (int32_t i = 0; i < count; ++i) {
+    const cur_item& it = items[i];
+    cur_status st = check_matrix((cur_dtype)it.dtype, it.A, it.m, it.n, it.lda, it.r);
+    if (st != CUR_OK) return arg_error("item " + std::to_string(i) + ": " + last_error());
+    if (!it.I || !it.J) return arg_error("item " + std::to_string(i) + ": I and J must be non-NULL");
+    cur_opts o;
+    st = resolve_opts(opts, (cur_dtype)it.dtype, it.r, it.n, &o);
+    if (st != CUR_OK) return arg_error("item " + std::to_string(i) + ": " + last_error());
+  }
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  cur_status worst = CUR_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    const cur_item& it = items[i];
+    cur_opts o;
+    resolve_opts(opts, (cur_dtype)it.dtype, it.r, it.n, &o);
+    cur_status st = select_dispatch(ctx, (cur_dtype)it.dtype, it.A, it.m, it.n, it.lda, it.r, o, it.I, it.J,
+                                    nullptr);
+    if (per_item) per_item[i] = st;
+    if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+    else if (worst == CUR_OK && st > 0) worst = st;
+  }
+  return worst;
+}
+
+}  // extern "C"

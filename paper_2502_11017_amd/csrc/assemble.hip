@@ -1,0 +1,187 @@
+// CUR assembly (Sec. 1.1): C = A(:,J), R = A(I,:), U = A(I,J)^+.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "cur_device.hpp"
+#include "cur_internal.hpp"
+
+namespace cur {
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_C(const T* __restrict__ A, int64_t m, int64_t lda,
+                                                       int r, const int64_t* __restrict__ J, T* C) {
+  const int64_t total = m * r;
+  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = idx / r;
+    const int k = (int)(idx - i * r);
+    C[idx] = A[i * lda + J[k]];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_R(const T* __restrict__ A, int64_t n, int64_t lda,
+                                                       const int64_t* __restrict__ I, T* R) {
+  const int k = blockIdx.y;
+  const T* src = A + I[k] * lda;
+  T* dst = R + (int64_t)k * n;
+  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads)
+    dst[j] = src[j];
+}
+
+template <int RMAX>
+struct AsmLds {
+  static constexpr int CH = RMAX <= 64 ? RMAX : 16;
+  double A[RMAX * RMAX];
+  double B[RMAX * CH];
+  double lk[RMAX];
+  int perm[RMAX];
+  int spiv;
+  int pinv;
+  double cs[2];
+  int rot;
+};
+
+// U = A(I,J)^{-1} by LU with partial pivoting, or the Jacobi pseudo-inverse
+// when a pivot is zero or min|u_kk|/max|u_kk| < r 2^-52.  W, V: r x r global
+// scratch for the Jacobi path.  flag[0] <- 1 if the pseudo-inverse was used.
+template <typename T, int RMAX>
+__global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A, int64_t lda, int r,
+                                                         const int64_t* I, const int64_t* J, double* U,
+                                                         double* W, double* V, double* sg, int* flag) {
+  __shared__ AsmLds<RMAX> L;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < r * r; idx += kThreads) {
+    const int a = idx / r, b = idx % r;
+    L.A[idx] = (double)A[I[a] * lda + J[b]];
+  }
+  __syncthreads();
+  const bool ok = block_gepp(L.A, r, L.perm, L.lk, &L.spiv);
+  if (tid == 0) {
+    int use_pinv = 1;
+    if (ok) {
+      double umin = HUGE_VAL, umax = 0.0;
+      for (int k = 0; k < r; ++k) {
+        const double u = fabs(L.A[k * r + k]);
+        umin = fmin(umin, u);
+        umax = fmax(umax, u);
+      }
+      use_pinv = (umin / umax < (double)r * 0x1p-52) ? 1 : 0;
+    }
+    L.pinv = use_pinv;
+    flag[0] = use_pinv;
+  }
+  __syncthreads();
+  if (!L.pinv) {
+    block_lu_inverse(L.A, L.perm, r, L.B, AsmLds<RMAX>::CH, U);
+    return;
+  }
+  // ---- one-sided Jacobi: W = G V with orthogonal columns (cyclic pairs, <= 60 sweeps)
+  for (int idx = tid; idx < r * r; idx += kThreads) {
+    const int a = idx / r, b = idx % r;
+    W[idx] = (double)A[I[a] * lda + J[b]];
+    V[idx] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) L.rot = 0;
+    __syncthreads();
+    for (int p = 0; p < r - 1; ++p)
+      for (int q = p + 1; q < r; ++q) {
+        if (tid == 0) {
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = 0; i < r; ++i) {
+            const double wp = W[i * r + p], wq = W[i * r + q];
+            al = fma(wp, wp, al);
+            be = fma(wq, wq, be);
+            ga = fma(wp, wq, ga);
+          }
+          L.cs[0] = 0.0;
+          L.cs[1] = 0.0;
+          if (!(ga == 0.0 || fabs(ga) <= 0x1p-52 * sqrt(al * be))) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            L.cs[0] = c;
+            L.cs[1] = c * t;
+            L.rot = 1;
+          }
+        }
+        __syncthreads();
+        const double c = L.cs[0], s = L.cs[1];
+        if (c != 0.0) {
+          for (int i = tid; i < r; i += kThreads) {
+            const double wp = W[i * r + p], wq = W[i * r + q];
+            W[i * r + p] = c * wp - s * wq;
+            W[i * r + q] = s * wp + c * wq;
+            const double vp = V[i * r + p], vq = V[i * r + q];
+            V[i * r + p] = c * vp - s * vq;
+            V[i * r + q] = s * vp + c * vq;
+          }
+        }
+        __syncthreads();
+      }
+    if (!L.rot) break;
+  }
+  if (tid == 0) {
+    double smax = 0.0;
+    for (int j = 0; j < r; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < r; ++i) s = fma(W[i * r + j], W[i * r + j], s);
+      sg[j] = sqrt(s);
+      smax = fmax(smax, sg[j]);
+    }
+    L.cs[0] = (double)r * 0x1p-52 * smax;
+  }
+  __syncthreads();
+  const double cut = L.cs[0];
+  for (int idx = tid; idx < r * r; idx += kThreads) {
+    const int a = idx / r, b = idx % r;
+    double s = 0.0;
+    for (int j = 0; j < r; ++j) {
+      if (!(sg[j] > cut)) continue;
+      s = fma(V[a * r + j], W[b * r + j] / (sg[j] * sg[j]), s);
+    }
+    U[idx] = s;
+  }
+}
+
+template <typename T>
+static cur_status assemble_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
+                                const int64_t* I, const int64_t* J, T* C, double* U, T* R) {
+  hipStream_t s = ctx->stream;
+  const size_t scratch = 3 * (size_t)r * r * sizeof(double) + 4096;
+  cur_status st = ensure_arena(ctx, scratch);
+  if (st != CUR_OK) return st;
+  char* base = (char*)ctx->arena;
+  int* flag = (int*)base;
+  double* W = (double*)(base + 4096);
+  double* V = W + (size_t)r * r;
+  double* sg = V + (size_t)r * r;
+  const int gc = (int)std::min<int64_t>((m * r + kThreads - 1) / kThreads, 8192);
+  hipLaunchKernelGGL((k_gather_C<T>), dim3(std::max(gc, 1)), dim3(kThreads), 0, s, A, m, lda, r, J, C);
+  const int gr = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 1024);
+  hipLaunchKernelGGL((k_gather_R<T>), dim3(std::max(gr, 1), r), dim3(kThreads), 0, s, A, n, lda, I, R);
+  if (r <= 32)
+    hipLaunchKernelGGL((k_assemble_U<T, 32>), dim3(1), dim3(kThreads), 0, s, A, lda, r, I, J, U, W, V, sg, flag);
+  else if (r <= 64)
+    hipLaunchKernelGGL((k_assemble_U<T, 64>), dim3(1), dim3(kThreads), 0, s, A, lda, r, I, J, U, W, V, sg, flag);
+  else
+    hipLaunchKernelGGL((k_assemble_U<T, 128>), dim3(1), dim3(kThreads), 0, s, A, lda, r, I, J, U, W, V, sg, flag);
+  CUR_HIP_CHECK(hipGetLastError());
+  int hflag = 0;
+  CUR_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  CUR_HIP_CHECK(hipStreamSynchronize(s));
+  ctx->last_pinv = hflag;
+  return CUR_OK;
+}
+
+cur_status assemble_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                             int r, const int64_t* I, const int64_t* J, void* C, double* U, void* R) {
+  if (dtype == CUR_F64)
+    return assemble_impl<double>(ctx, (const double*)A, m, n, lda, r, I, J, (double*)C, U, (double*)R);
+  return assemble_impl<float>(ctx, (const float*)A, m, n, lda, r, I, J, (float*)C, U, (float*)R);
+}
+
+}  // namespace cur

@@ -1,0 +1,133 @@
+// Internal declarations of libcur (HIP, gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/cur.h"
+
+namespace cur {
+
+constexpr int kThreads = 256;      // threads per workgroup of every kernel here
+constexpr int kTileRows = 256;     // rows of a row-pass tile (one row per thread)
+constexpr int kMetaFields = 10;    // fields of a cur_trace meta record
+
+// Per-node state machine.  A node is a leaf (one column block), a merge of two
+// children, or a promoted copy of an odd last child.
+enum NodeState : int32_t {
+  ST_DONE = 0,
+  ST_ACA = 1,        // next pass: ACA step (apply pending pivot, then argmax)
+  ST_ROW_FRESH = 2,  // next pass: B = A(:,J) X fresh, then argmax
+  ST_ROW_SWAP = 3,   // next pass: apply pending row swap to B, then argmax
+  ST_START_SWAP = 4, // next ctl: start the swap loop (ROW phase start)
+};
+
+enum NodeKind : int32_t { KIND_LEAF = 0, KIND_MERGE = 1, KIND_PROMOTED = 2 };
+
+// Winner of one row tile in a pass.
+struct Partial {
+  double val;   // |x| (the magnitude compared)
+  double sval;  // x   (signed value in the working precision, widened)
+  int64_t key;  // scan-order key: smaller wins ties
+  int64_t row;  // row index
+  int32_t pos;  // column position in the working layout
+  int32_t pad;
+};
+
+struct Node {
+  // ---- geometry and buffers (set by the host) ----
+  int64_t m;         // rows of A
+  int32_t r;         // rank
+  int32_t ncmax;     // capacity of the candidate arrays
+  int32_t ntiles;    // row tiles of a pass
+  int32_t smax;      // swap budget
+  int32_t kind;      // NodeKind
+  int32_t child0, child1;  // indices into the previous level's node table (-1: none)
+  int32_t pad0;
+  double tau;        // swap iff |B| > 1 + tau
+  double theta;      // numerical-zero pivot threshold of ACA
+  void* panel;       // m x ncmax, column-major (ld m), element T: A(:, Jc)
+  void* work;        // m x max(ncmax, r), column-major: ACA residual, then B
+  double* X;         // r x r row-major: A(I,J)^{-1}
+  double* Bc;        // r x ncmax row-major: column interpolation matrix
+  double* vec;       // max(ncmax, r): pivot-row factors f (ACA) or v (row swap)
+  Partial* part;     // ntiles
+  double* prow;      // ntiles x max(ncmax, r): winner row of each tile
+  int64_t* Jc;       // ncmax: original column index of each candidate (ascending)
+  int32_t* colmap;   // ncmax: ACA layout position -> candidate position
+  int32_t* srcpos;   // ncmax: merge: (child << 24) | position in the child's panel
+  uint8_t* insel;    // ncmax: candidate currently in J
+  int64_t* I;        // r: selected rows (current order)
+  int32_t* Jp;       // r: selected candidate positions (current order)
+  // ---- dynamic state (device) ----
+  int32_t nc;        // number of candidates
+  int32_t st;        // NodeState
+  int32_t t;         // ACA pivots accepted
+  int32_t q;         // pivots held (r unless rank-short)
+  int32_t steps;     // ACA step limit min(r, nc, m)
+  int32_t na;        // ACA: active columns of the layout the next pass reads
+  int32_t is_short, nocap, err, phase;
+  int32_t phase_swaps, since, swaps, phases, refreshes;
+  int32_t pend_k;    // pending pivot column position (ACA) / slot k* (row swap)
+  int64_t pend_i;    // pending pivot row
+  double pend_p;     // pending pivot value
+  double vol_m;      // volume mantissa (finished nodes)
+  int32_t vol_e;     // volume exponent
+  int32_t pad1;
+};
+
+// Host-side error reporting (thread-local last error).
+void set_error(const std::string& msg);
+const char* last_error();
+
+#define CUR_HIP_CHECK(expr)                                                           \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      ::cur::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));            \
+      return CUR_ERR_DEVICE;                                                          \
+    }                                                                                 \
+  } while (0)
+
+}  // namespace cur
+
+// Context (opaque to callers).
+struct cur_ctx_s {
+  int device;
+  hipStream_t stream;
+  bool own_stream;
+  void* arena;          // device workspace
+  size_t arena_bytes;
+  int32_t* host_flag;   // pinned host word for polling
+  int cu_count;
+  int last_pinv;        // cur_assemble used the pseudo-inverse
+};
+
+namespace cur {
+// Bump allocator over the context arena; sizes are rounded to 256 bytes.
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t off;
+  void* take(size_t bytes) {
+    size_t b = (bytes + 255) & ~size_t(255);
+    if (off + b > cap) return nullptr;
+    void* p = base + off;
+    off += b;
+    return p;
+  }
+};
+cur_status ensure_arena(cur_ctx ctx, size_t bytes);
+
+cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
+                           int64_t lda, int r, const cur_opts& o, int64_t* I, int64_t* J,
+                           cur_info* info);
+cur_status assemble_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
+                             int64_t lda, int r, const int64_t* I, const int64_t* J, void* C,
+                             double* U, void* R);
+cur_status residual_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
+                             int64_t lda, int r, const void* C, const double* U, const void* R,
+                             int prec, double* cheb, double* fro_rel);
+}  // namespace cur

@@ -1,0 +1,1201 @@
+// Maximal-volume CUR selection on gfx950: column-block leaves started by
+// adaptive cross approximation (Alg. 1), maxvol row/column swap phases, and a
+// binary merge tree over the blocks (Alg. 3 block partition, merged pairwise).
+//
+// Execution model.  A tree level is a table of nodes.  The host repeats two
+// launches until every node of the level is finished:
+//   k_pass  grid (row tiles x nodes): the bandwidth-bound sweep over a node's
+//           m x (active columns) working matrix -- an ACA rank-1 update, a row
+//           swap (Sherman-Morrison) update, or a fresh B = A(:,J) A(I,J)^-1 --
+//           fused with the per-tile argmax of the next decision;
+//   k_ctl   one workgroup per node: reduces the tile winners (the global
+//           maximum of Alg. 3), takes the decision of the documented algorithm
+//           and does the small serial work (r x r LU in LDS, inverse, the
+//           column phase on the r x |Jc| matrix, sorting, the final volume).
+// No kernel waits on another workgroup, so every launch ends by construction;
+// the host bounds the number of iterations.
+//
+// Layouts: every node keeps its candidate columns A(:, Jc) as a compact
+// column-major panel (m x |Jc|, leading dimension m) so that every pass reads
+// and writes whole columns with unit stride across a wavefront.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cur_device.hpp"
+#include "cur_internal.hpp"
+
+namespace cur {
+
+// Rows per thread block of the transposing panel copy.
+constexpr int kTR = 64;
+
+// ---------------------------------------------------------------- a0: input scan
+// max|A| over the matrix and a non-finite flag.  out[0]: max bits (non-negative
+// doubles order like their bit patterns), out[1]: non-finite flag.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_amax(const T* __restrict__ A, int64_t m, int64_t n,
+                                                   int64_t lda, unsigned long long* out) {
+  double mx = 0.0;
+  int bad = 0;
+  const int64_t total = m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx - i * n;
+    const double v = (double)A[i * lda + j];
+    if (!isfinite(v)) bad = 1;
+    else mx = fmax(mx, fabs(v));
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, s, 64));
+    bad |= __shfl_xor(bad, s, 64);
+  }
+  __shared__ double smx[kThreads / 64];
+  __shared__ int sbad[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) {
+    smx[threadIdx.x >> 6] = mx;
+    sbad[threadIdx.x >> 6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) {
+      mx = fmax(mx, smx[w]);
+      bad |= sbad[w];
+    }
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(mx));
+    if (bad) atomicOr(&out[1], 1ull);
+  }
+}
+
+// ---------------------------------------------------------------- leaf set-up
+// panel(:, c) = A(:, c0 + c) for the leaf's block, transposed through LDS.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes, const T* __restrict__ A,
+                                                           int64_t lda, const int64_t* col0) {
+  Node& nd = nodes[blockIdx.z];
+  const int64_t m = nd.m;
+  const int nc = nd.nc;
+  const int64_t r0 = (int64_t)blockIdx.x * kTR;
+  const int cb = blockIdx.y * 64;
+  if (r0 >= m || cb >= nc) return;
+  __shared__ T tile[kTR][65];
+  const int64_t c0 = col0[blockIdx.z];
+  // read kTR rows x 64 columns, lanes along the row
+  for (int idx = threadIdx.x; idx < kTR * 64; idx += kThreads) {
+    const int rr = idx >> 6, cc = idx & 63;
+    const int64_t i = r0 + rr;
+    if (i < m && cb + cc < nc) tile[rr][cc] = A[i * lda + c0 + cb + cc];
+  }
+  __syncthreads();
+  T* P = (T*)nd.panel;
+  for (int idx = threadIdx.x; idx < kTR * 64; idx += kThreads) {
+    const int cc = idx / kTR, rr = idx % kTR;
+    const int64_t i = r0 + rr;
+    if (i < m && cb + cc < nc) P[(int64_t)(cb + cc) * m + i] = tile[rr][cc];
+  }
+}
+
+// Leaf candidate lists: Jc = c0 + [0, nc), identity layout map.
+__global__ void k_leaf_init(Node* nodes, const int64_t* col0) {
+  Node& nd = nodes[blockIdx.x];
+  for (int c = threadIdx.x; c < nd.nc; c += blockDim.x) {
+    nd.Jc[c] = col0[blockIdx.x] + c;
+    nd.colmap[c] = c;
+  }
+}
+
+// ---------------------------------------------------------------- merge set-up
+// One workgroup per node of the new level.  Promoted nodes copy their child.
+// Merges form Jc as the sorted union of the children's selected columns, the
+// source map of the panel, and the starting (I, J) from the child of larger
+// volume (exact tie: left), or prepare an ACA start when both children are
+// rank-short.
+__global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node* prev,
+                                                         int32_t* done) {
+  Node& nd = nodes[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int r = nd.r;
+  if (nd.kind == KIND_PROMOTED) {
+    const Node& c = prev[nd.child0];
+    for (int k = tid; k < r; k += blockDim.x) {
+      nd.I[k] = c.I[k];
+      nd.Jp[k] = c.Jp[k];
+    }
+    if (tid == 0) {
+      nd.nc = c.nc;
+      nd.q = c.q;
+      nd.t = c.t;
+      nd.is_short = c.is_short;
+      nd.vol_m = c.vol_m;
+      nd.vol_e = c.vol_e;
+      nd.err = c.err;
+      nd.st = ST_DONE;
+      atomicAdd(done, 1);
+    }
+    return;
+  }
+  const Node& L = prev[nd.child0];
+  const Node& R = prev[nd.child1];
+  if (tid == 0) {
+    const int qL = L.q, qR = R.q;
+    // sorted merge of two ascending lists of original column indices
+    int a = 0, b = 0, c = 0;
+    while (a < qL || b < qR) {
+      const int64_t ja = a < qL ? L.Jc[L.Jp[a]] : INT64_MAX;
+      const int64_t jb = b < qR ? R.Jc[R.Jp[b]] : INT64_MAX;
+      if (ja < jb) {
+        nd.Jc[c] = ja;
+        nd.srcpos[c] = (0 << 24) | L.Jp[a];
+        nd.colmap[c] = a;  // temporary: rank inside the left child's J
+        ++a;
+      } else {
+        nd.Jc[c] = jb;
+        nd.srcpos[c] = (1 << 24) | R.Jp[b];
+        nd.colmap[c] = (1 << 24) | b;
+        ++b;
+      }
+      ++c;
+    }
+    nd.nc = c;
+    nd.swaps = nd.phases = nd.refreshes = 0;
+    nd.nocap = nd.err = 0;
+    nd.phase = nd.phase_swaps = nd.since = 0;
+    nd.vol_m = 0.0;
+    nd.vol_e = 0;
+    if (!L.is_short || !R.is_short) {
+      int src = 0;
+      if (!L.is_short && !R.is_short) {
+        const bool rg = (R.vol_e != L.vol_e) ? (R.vol_e > L.vol_e) : (R.vol_m > L.vol_m);
+        src = rg ? 1 : 0;
+      } else {
+        src = L.is_short ? 1 : 0;
+      }
+      const Node& S = src ? R : L;
+      for (int k = 0; k < r; ++k) nd.I[k] = S.I[k];
+      // positions of the chosen child's columns in the merged list
+      for (int cc = 0; cc < c; ++cc) {
+        const int tag = nd.colmap[cc];
+        if ((tag >> 24) == src) nd.Jp[tag & 0xffffff] = cc;
+      }
+      nd.is_short = 0;
+      nd.q = r;
+      nd.t = r;
+      nd.st = ST_START_SWAP;
+    } else {
+      nd.steps = min(r, c);
+      if ((int64_t)nd.steps > nd.m) nd.steps = (int)nd.m;
+      nd.is_short = 0;
+      nd.q = 0;
+      nd.t = 0;
+      nd.na = c;
+      if (nd.steps == 0) {
+        nd.is_short = 1;
+        nd.st = ST_DONE;
+        atomicAdd(done, 1);
+      } else {
+        nd.st = ST_ACA;
+      }
+    }
+  }
+  __syncthreads();
+  if (nd.st == ST_ACA)
+    for (int cc = tid; cc < nd.nc; cc += blockDim.x) nd.colmap[cc] = cc;
+}
+
+// parent panel column c = child panel column (srcpos), for all merge nodes
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_panel_build(Node* nodes, const Node* prev) {
+  Node& nd = nodes[blockIdx.z];
+  if (nd.kind != KIND_MERGE) return;
+  const int c = blockIdx.y;
+  if (c >= nd.nc) return;
+  const int sp = nd.srcpos[c];
+  const Node& ch = prev[(sp >> 24) ? nd.child1 : nd.child0];
+  const T* src = (const T*)ch.panel + (int64_t)(sp & 0xffffff) * nd.m;
+  T* dst = (T*)nd.panel + (int64_t)c * nd.m;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nd.m;
+       i += (int64_t)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- the pass
+// ACA step, fresh B, or row swap over one tile of kTileRows rows, fused with the
+// tile's argmax.  Writes the tile winner and its full row (in the layout the
+// next step reads) to the node's partial arrays.
+template <typename T, int RMAX>
+__global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
+  Node& nd = nodes[blockIdx.y];
+  const int st = nd.st;
+  if (st != ST_ACA && st != ST_ROW_FRESH && st != ST_ROW_SWAP) return;
+  const int tile = blockIdx.x;
+  if (tile >= nd.ntiles) return;
+  const int64_t m = nd.m;
+  const int r = nd.r;
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)tile * kTileRows;
+  const int64_t row = row0 + tid;
+  const bool valid = row < m;
+  T* W = (T*)nd.work;
+  const T* P = (const T*)nd.panel;
+
+  constexpr int CB = 16;  // columns of X staged per chunk (fresh B)
+  __shared__ double sX[RMAX * CB];
+  __shared__ int sJp[RMAX];
+  __shared__ int sslot[kTileRows];
+  __shared__ Cand sc[kThreads / 64];
+
+  Cand best = cand_none();
+  const T* rowsrc = W;
+  int rowlen = r;
+
+  if (st == ST_ACA) {
+    const int t = nd.t, na = nd.na, nc = nd.nc;
+    const int32_t* cmap = nd.colmap;
+    const T* src = (t <= 1) ? P : W;
+    if (t == 0) {
+      if (valid)
+        for (int c = 0; c < na; ++c) {
+          const T x = src[(int64_t)c * m + row];
+          Cand o;
+          o.val = fabs((double)x);
+          o.sval = (double)x;
+          o.key = row * nc + cmap[c];
+          o.row = row;
+          o.pos = c;
+          cand_take(best, o);
+        }
+      rowsrc = P;
+      rowlen = na;
+    } else {
+      const int pc = nd.pend_k;
+      const int64_t pi = nd.pend_i;
+      const double* f = nd.vec;
+      if (valid) {
+        const T g = src[(int64_t)pc * m + row];
+        for (int c = 0; c < na; ++c) {
+          if (c == pc) continue;
+          T x = src[(int64_t)c * m + row];
+          x = fma_t<T>(-g, (T)f[c], x);
+          if (row == pi) x = (T)0;
+          const int np = (c == na - 1) ? pc : c;
+          W[(int64_t)np * m + row] = x;
+          Cand o;
+          o.val = fabs((double)x);
+          o.sval = (double)x;
+          o.key = row * nc + cmap[c];
+          o.row = row;
+          o.pos = np;
+          cand_take(best, o);
+        }
+      }
+      rowsrc = W;
+      rowlen = na - 1;
+    }
+  } else {
+    // masked rows: the selected ones, with their slot k
+    sslot[tid] = -1;
+    __syncthreads();
+    for (int k = tid; k < r; k += kThreads) {
+      const int64_t i = nd.I[k];
+      if (i >= row0 && i < row0 + kTileRows) sslot[i - row0] = k;
+      sJp[k] = nd.Jp[k];
+    }
+    __syncthreads();
+    const int slot = sslot[tid];
+    if (st == ST_ROW_FRESH) {
+      for (int c0 = 0; c0 < r; c0 += CB) {
+        const int nb = min(CB, r - c0);
+        __syncthreads();
+        for (int idx = tid; idx < r * CB; idx += kThreads) {
+          const int k = idx / CB, j = idx % CB;
+          sX[idx] = (j < nb) ? nd.X[(int64_t)k * r + c0 + j] : 0.0;
+        }
+        __syncthreads();
+        if (valid) {
+          double acc[CB];
+#pragma unroll
+          for (int j = 0; j < CB; ++j) acc[j] = 0.0;
+          for (int k = 0; k < r; ++k) {
+            const double pk = (double)P[(int64_t)sJp[k] * m + row];
+#pragma unroll
+            for (int j = 0; j < CB; ++j) acc[j] = fma(pk, sX[k * CB + j], acc[j]);
+          }
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            if (j >= nb) break;
+            const int c = c0 + j;
+            T b = (T)acc[j];
+            if (slot >= 0) b = (c == slot) ? (T)1 : (T)0;
+            W[(int64_t)c * m + row] = b;
+            if (slot < 0) {
+              Cand o;
+              o.val = fabs((double)b);
+              o.sval = (double)b;
+              o.key = row * r + c;
+              o.row = row;
+              o.pos = c;
+              cand_take(best, o);
+            }
+          }
+        }
+      }
+    } else {
+      const int ks = nd.pend_k;
+      const int64_t is = nd.pend_i;
+      const double* v = nd.vec;
+      if (valid) {
+        const T g = W[(int64_t)ks * m + row];
+        for (int c = 0; c < r; ++c) {
+          T b = W[(int64_t)c * m + row];
+          b = fma_t<T>(-g, (T)v[c], b);
+          if (row == is) b = (c == ks) ? (T)1 : (T)0;
+          W[(int64_t)c * m + row] = b;
+          if (slot < 0) {
+            Cand o;
+            o.val = fabs((double)b);
+            o.sval = (double)b;
+            o.key = row * r + c;
+            o.row = row;
+            o.pos = c;
+            cand_take(best, o);
+          }
+        }
+      }
+    }
+    rowsrc = W;
+    rowlen = r;
+  }
+
+  best = block_argmax(best, sc);
+  if (tid == 0) {
+    Partial p;
+    p.val = best.val;
+    p.sval = best.sval;
+    p.key = best.key;
+    p.row = best.row;
+    p.pos = best.pos;
+    p.pad = 0;
+    nd.part[tile] = p;
+  }
+  if (best.row >= 0) {
+    const int ld = max(nd.ncmax, r);
+    double* pr = nd.prow + (int64_t)tile * ld;
+    for (int c = tid; c < rowlen; c += kThreads) pr[c] = (double)rowsrc[(int64_t)c * m + best.row];
+  }
+}
+
+// ---------------------------------------------------------------- the controller
+enum CtlMode : int32_t {
+  M_EXIT = 0,
+  M_ROW_START = 100,
+  M_ROW_END = 101,
+  M_COL = 102,
+  M_FINISH = 103,
+  M_FINISH_SHORT = 104,
+  M_REFRESH = 105,
+  M_SWAPVEC = 106,
+};
+
+struct CtlShared {
+  int mode;
+  int st, t, q, na, steps, nc;
+  int is_short, nocap, err, phase, phase_swaps, since, swaps, phases, refreshes;
+  int pend_k;
+  int64_t pend_i;
+  double pend_p;
+  double vol_m;
+  int vol_e;
+  int spiv;
+  int wtile;
+  Cand win;
+};
+
+template <typename T, int RMAX>
+struct CtlLds {
+  static constexpr int CH = RMAX <= 64 ? RMAX : 16;  // inverse column chunk
+  double A[RMAX * RMAX];   // G / LU, later X
+  double B[RMAX * CH];     // inverse chunk, later columns of A(I, Jc)
+  double lk[RMAX];
+  int perm[RMAX];
+  int64_t tmp64[RMAX];
+  int tmp32[RMAX];
+  Cand sc[kThreads / 64];
+  CtlShared s;
+};
+
+// Reduce the tile winners of the last pass (the global argmax of the node).
+template <typename T, int RMAX>
+__device__ void ctl_reduce(Node& nd, CtlLds<T, RMAX>& L) {
+  Cand b = cand_none();
+  for (int tl = threadIdx.x; tl < nd.ntiles; tl += kThreads) {
+    const Partial p = nd.part[tl];
+    Cand o;
+    o.val = p.val;
+    o.sval = p.sval;
+    o.key = p.key;
+    o.row = p.row;
+    o.pos = p.pos;
+    cand_take(b, o);
+  }
+  b = block_argmax(b, L.sc);
+  if (threadIdx.x == 0) {
+    L.s.win = b;
+    L.s.wtile = b.row >= 0 ? (int)(b.row / kTileRows) : -1;
+  }
+  __syncthreads();
+}
+
+// G = A(I, J) for the current orders, LU, X = G^{-1} to nd.X; optionally the
+// volume instead of X.  Returns false on a singular G.
+template <typename T, int RMAX>
+__device__ bool ctl_build(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_vol) {
+  const int r = nd.r;
+  const int64_t m = nd.m;
+  const T* P = (const T*)nd.panel;
+  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
+    const int a = idx / r, b = idx % r;
+    L.A[idx] = (double)P[(int64_t)nd.Jp[b] * m + nd.I[a]];
+  }
+  __syncthreads();
+  if (!block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv)) return false;
+  if (want_vol && threadIdx.x == 0) lu_volume(L.A, r, &L.s.vol_m, &L.s.vol_e);
+  if (want_X) block_lu_inverse(L.A, L.perm, r, L.B, CtlLds<T, RMAX>::CH, nd.X);
+  __syncthreads();
+  return true;
+}
+
+template <typename T, int RMAX>
+__device__ void ctl_sort_IJ(Node& nd, CtlLds<T, RMAX>& L, int n) {
+  block_sort<int64_t>(nd.I, n, L.tmp64);
+  block_sort<int32_t>(nd.Jp, n, L.tmp32);
+}
+
+// Fresh column interpolation matrix Bc = X A(I, Jc) (r x nc, row-major, ld ncmax),
+// sums over k ascending, then column Jp[k] := e_k.  X is in L.A.
+template <typename T, int RMAX>
+__device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L) {
+  const int r = nd.r, nc = L.s.nc, ld = nd.ncmax;
+  const int64_t m = nd.m;
+  const T* P = (const T*)nd.panel;
+  constexpr int CH = CtlLds<T, RMAX>::CH;
+  for (int c0 = 0; c0 < nc; c0 += CH) {
+    const int nb = min(CH, nc - c0);
+    for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
+      const int k = idx / nb, j = idx % nb;
+      L.B[k * CH + j] = (double)P[(int64_t)(c0 + j) * m + nd.I[k]];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
+      const int a = idx / nb, j = idx % nb;
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s = fma(L.A[a * r + k], L.B[k * CH + j], s);
+      nd.Bc[(int64_t)a * ld + c0 + j] = s;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
+    const int k = idx / r, a = idx % r;
+    nd.Bc[(int64_t)a * ld + nd.Jp[k]] = (a == k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+}
+
+// Load X (written by block_lu_inverse to nd.X) into L.A.
+template <typename T, int RMAX>
+__device__ void ctl_load_X(Node& nd, CtlLds<T, RMAX>& L) {
+  const int r = nd.r;
+  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
+  __syncthreads();
+}
+
+// The whole COL phase of one node (maxvol on A(I, Jc)^T with I fixed).
+// Returns after the phase; L.s.mode is set to the follow-up.
+template <typename T, int RMAX>
+__device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
+  const int r = nd.r, nc = L.s.nc, ld = nd.ncmax, tid = threadIdx.x;
+  ctl_sort_IJ(nd, L, r);
+  if (tid == 0) {
+    L.s.phase_swaps = 0;
+    L.s.since = 0;
+  }
+  __syncthreads();
+  if (nc > r) {
+    for (int c = tid; c < nc; c += kThreads) nd.insel[c] = 0;
+    __syncthreads();
+    for (int k = tid; k < r; k += kThreads) nd.insel[nd.Jp[k]] = 1;
+    if (!ctl_build(nd, L, true, false)) {
+      if (tid == 0) L.s.err = CUR_ERR_INTERNAL;
+    } else {
+      ctl_load_X(nd, L);
+      ctl_fresh_bc(nd, L);
+      if (tid == 0) L.s.refreshes++;
+      __syncthreads();
+      for (int guard = 0; guard < (1 << 30); ++guard) {
+        Cand b = cand_none();
+        for (int idx = tid; idx < r * nc; idx += kThreads) {
+          const int c = idx / r, k = idx % r;
+          if (nd.insel[c]) continue;
+          const double x = nd.Bc[(int64_t)k * ld + c];
+          Cand o;
+          o.val = fabs(x);
+          o.sval = x;
+          o.key = (int64_t)c * r + k;
+          o.row = k;
+          o.pos = c;
+          cand_take(b, o);
+        }
+        b = block_argmax(b, L.sc);
+        if (b.row < 0 || b.val <= lim) {
+          if (L.s.since == 0) break;
+          if (!ctl_build(nd, L, true, false)) {
+            if (tid == 0) L.s.err = CUR_ERR_INTERNAL;
+            break;
+          }
+          ctl_load_X(nd, L);
+          ctl_fresh_bc(nd, L);
+          if (tid == 0) {
+            L.s.refreshes++;
+            L.s.since = 0;
+          }
+          __syncthreads();
+          continue;
+        }
+        if (L.s.swaps >= nd.smax) {
+          if (tid == 0) L.s.nocap = 1;
+          __syncthreads();
+          break;
+        }
+        // swap candidate column c* into slot k*
+        const int ks = (int)b.row, cs = b.pos;
+        const double p = b.sval;
+        double* wv = nd.vec;              // w (r)
+        double* rowk = nd.vec + RMAX;     // old row k* of Bc (nc)
+        for (int a = tid; a < r; a += kThreads) {
+          const double x = nd.Bc[(int64_t)a * ld + cs];
+          wv[a] = (a == ks) ? (p - 1.0) / p : x / p;
+        }
+        for (int c = tid; c < nc; c += kThreads) rowk[c] = nd.Bc[(int64_t)ks * ld + c];
+        __syncthreads();
+        for (int idx = tid; idx < r * nc; idx += kThreads) {
+          const int a = idx / nc, c = idx % nc;
+          double x = fma(-wv[a], rowk[c], nd.Bc[(int64_t)a * ld + c]);
+          if (c == cs) x = (a == ks) ? 1.0 : 0.0;
+          nd.Bc[(int64_t)a * ld + c] = x;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          nd.insel[nd.Jp[ks]] = 0;
+          nd.insel[cs] = 1;
+          nd.Jp[ks] = cs;
+          L.s.swaps++;
+          L.s.phase_swaps++;
+          L.s.since++;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    L.s.phases++;
+    if (L.s.err || L.s.nocap || L.s.phase_swaps == 0) {
+      L.s.mode = M_FINISH;
+    } else {
+      L.s.phase++;
+      L.s.mode = M_ROW_START;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int RMAX>
+__global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, int startup) {
+  Node& nd = nodes[blockIdx.x];
+  if (nd.st == ST_DONE) return;
+  // the start-up launch only opens swap loops; pass states wait for their pass
+  if (startup && nd.st != ST_START_SWAP) return;
+  __shared__ CtlLds<T, RMAX> L;
+  const int tid = threadIdx.x;
+  const int r = nd.r;
+  const int64_t m = nd.m;
+  const double lim = 1.0 + nd.tau;
+  if (tid == 0) {
+    CtlShared& s = L.s;
+    s.st = nd.st; s.t = nd.t; s.q = nd.q; s.na = nd.na; s.steps = nd.steps; s.nc = nd.nc;
+    s.is_short = nd.is_short; s.nocap = nd.nocap; s.err = nd.err; s.phase = nd.phase;
+    s.phase_swaps = nd.phase_swaps; s.since = nd.since; s.swaps = nd.swaps; s.phases = nd.phases;
+    s.refreshes = nd.refreshes; s.pend_k = nd.pend_k; s.pend_i = nd.pend_i; s.pend_p = nd.pend_p;
+    s.vol_m = nd.vol_m; s.vol_e = nd.vol_e;
+    s.mode = M_EXIT;
+  }
+  __syncthreads();
+  const int st0 = L.s.st;
+
+  // ---- consume the pass that just ran
+  if (st0 == ST_ACA) {
+    ctl_reduce(nd, L);
+    if (tid == 0) {
+      CtlShared& s = L.s;
+      const int na_read = s.na;
+      int na_new = na_read;
+      if (s.t > 0) {
+        const int pc = s.pend_k;
+        if (pc != na_read - 1) nd.colmap[pc] = nd.colmap[na_read - 1];
+        na_new = na_read - 1;
+      }
+      const Cand& w = s.win;
+      if (w.row < 0 || fabs(w.sval) <= nd.theta) {
+        s.q = s.t;
+        s.mode = M_FINISH_SHORT;
+      } else {
+        nd.I[s.t] = w.row;
+        nd.Jp[s.t] = nd.colmap[w.pos];
+        s.t++;
+        s.q = s.t;
+        if (s.t == s.steps) {
+          if (s.t == r) {
+            s.phase = 0;
+            s.mode = M_ROW_START;
+          } else {
+            s.mode = M_FINISH_SHORT;
+          }
+        } else {
+          s.pend_i = w.row;
+          s.pend_k = w.pos;
+          s.pend_p = w.sval;
+          s.na = na_new;
+          s.st = ST_ACA;
+          s.mode = M_EXIT;
+        }
+      }
+    }
+    __syncthreads();
+    if (L.s.mode == M_EXIT) {
+      // f_c = R(i*, c) / p in the working precision
+      const int ld = max(nd.ncmax, r);
+      const double* pr = nd.prow + (int64_t)L.s.wtile * ld;
+      const T p = (T)L.s.pend_p;
+      for (int c = tid; c < L.s.na; c += kThreads) nd.vec[c] = (double)((T)pr[c] / p);
+    }
+  } else if (st0 == ST_ROW_FRESH || st0 == ST_ROW_SWAP) {
+    ctl_reduce(nd, L);
+    if (tid == 0) {
+      CtlShared& s = L.s;
+      const Cand& w = s.win;
+      if (w.row < 0 || w.val <= lim) {
+        s.mode = (s.since == 0) ? M_ROW_END : M_REFRESH;
+      } else if (s.swaps >= nd.smax) {
+        s.nocap = 1;
+        s.mode = M_ROW_END;
+      } else {
+        s.pend_i = w.row;
+        s.pend_k = w.pos;
+        s.pend_p = w.sval;
+        nd.I[w.pos] = w.row;
+        s.swaps++;
+        s.phase_swaps++;
+        s.since++;
+        s.st = ST_ROW_SWAP;
+        s.mode = M_SWAPVEC;
+      }
+    }
+    __syncthreads();
+    if (L.s.mode == M_SWAPVEC) {
+      const int ld = max(nd.ncmax, r);
+      const double* pr = nd.prow + (int64_t)L.s.wtile * ld;
+      const T p = (T)L.s.pend_p;
+      const int ks = L.s.pend_k;
+      for (int c = tid; c < r; c += kThreads)
+        nd.vec[c] = (c == ks) ? (double)((p - (T)1) / p) : (double)((T)pr[c] / p);
+      __syncthreads();
+      if (tid == 0) L.s.mode = M_EXIT;
+      __syncthreads();
+    } else if (L.s.mode == M_REFRESH) {
+      // tentative stop after swaps: recompute B fresh for the current orders
+      if (!ctl_build(nd, L, true, false)) {
+        if (tid == 0) {
+          L.s.err = CUR_ERR_INTERNAL;
+          L.s.mode = M_ROW_END;
+        }
+      } else if (tid == 0) {
+        L.s.refreshes++;
+        L.s.since = 0;
+        L.s.st = ST_ROW_FRESH;
+        L.s.mode = M_EXIT;
+      }
+      __syncthreads();
+    }
+  } else if (st0 == ST_START_SWAP) {
+    if (tid == 0) {
+      L.s.phase = 0;
+      L.s.mode = M_ROW_START;
+    }
+    __syncthreads();
+  }
+
+  // ---- serial steps until a pass is needed or the node is finished
+  for (int guard = 0; guard < 64; ++guard) {
+    const int mode = L.s.mode;
+    if (mode == M_EXIT) break;
+    if (mode == M_ROW_START) {
+      ctl_sort_IJ(nd, L, r);
+      if (tid == 0) {
+        L.s.phase_swaps = 0;
+        L.s.since = 0;
+      }
+      __syncthreads();
+      if (m == r) {
+        if (tid == 0) L.s.mode = M_ROW_END;
+      } else if (!ctl_build(nd, L, true, false)) {
+        if (tid == 0) {
+          L.s.err = CUR_ERR_INTERNAL;
+          L.s.mode = M_ROW_END;
+        }
+      } else if (tid == 0) {
+        L.s.refreshes++;
+        L.s.st = ST_ROW_FRESH;
+        L.s.mode = M_EXIT;
+      }
+      __syncthreads();
+    } else if (mode == M_ROW_END) {
+      if (tid == 0) {
+        CtlShared& s = L.s;
+        s.phases++;
+        if (s.err || s.nocap || (s.phase >= 1 && s.phase_swaps == 0)) {
+          s.mode = M_FINISH;
+        } else {
+          s.phase++;
+          s.mode = M_COL;
+        }
+      }
+      __syncthreads();
+    } else if (mode == M_COL) {
+      ctl_col_phase(nd, L, lim);
+    } else if (mode == M_FINISH) {
+      ctl_sort_IJ(nd, L, r);
+      if (!L.s.err) {
+        if (!ctl_build(nd, L, false, true) && tid == 0) L.s.err = CUR_ERR_INTERNAL;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        L.s.st = ST_DONE;
+        L.s.mode = M_EXIT;
+        atomicAdd(done, 1);
+      }
+      __syncthreads();
+    } else if (mode == M_FINISH_SHORT) {
+      ctl_sort_IJ(nd, L, L.s.q);
+      if (tid == 0) {
+        L.s.is_short = 1;
+        L.s.st = ST_DONE;
+        L.s.mode = M_EXIT;
+        atomicAdd(done, 1);
+      }
+      __syncthreads();
+    } else {
+      if (tid == 0) {
+        L.s.err = CUR_ERR_INTERNAL;
+        L.s.st = ST_DONE;
+        L.s.mode = M_EXIT;
+        atomicAdd(done, 1);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const CtlShared& s = L.s;
+    nd.st = s.st; nd.t = s.t; nd.q = s.q; nd.na = s.na; nd.steps = s.steps;
+    nd.is_short = s.is_short; nd.nocap = s.nocap; nd.err = s.err; nd.phase = s.phase;
+    nd.phase_swaps = s.phase_swaps; nd.since = s.since; nd.swaps = s.swaps; nd.phases = s.phases;
+    nd.refreshes = s.refreshes; nd.pend_k = s.pend_k; nd.pend_i = s.pend_i; nd.pend_p = s.pend_p;
+    nd.vol_m = s.vol_m; nd.vol_e = s.vol_e;
+  }
+}
+
+// Root -> caller's I, J (ascending original indices, -1 padded).
+__global__ void k_finalize(const Node* root, int64_t* I, int64_t* J) {
+  const Node& nd = *root;
+  for (int k = threadIdx.x; k < nd.r; k += blockDim.x) {
+    const bool ok = k < nd.q;
+    I[k] = ok ? nd.I[k] : -1;
+    J[k] = ok ? nd.Jc[nd.Jp[k]] : -1;
+  }
+}
+
+// Per-node outputs for the host: original indices of I and J.
+__global__ void k_export(const Node* nodes, int64_t* I, int64_t* J, int r) {
+  const Node& nd = nodes[blockIdx.x];
+  for (int k = threadIdx.x; k < r; k += blockDim.x) {
+    const bool ok = k < nd.q && nd.st == ST_DONE;
+    I[(int64_t)blockIdx.x * r + k] = ok ? nd.I[k] : -1;
+    J[(int64_t)blockIdx.x * r + k] = ok ? nd.Jc[nd.Jp[k]] : -1;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+struct LevelPlan {
+  int count;
+  int first;  // index of the level's first node in the global table
+};
+
+struct SelectPlan {
+  int r, w;
+  int64_t m, n;
+  int b;
+  std::vector<LevelPlan> levels;
+  int total_nodes;
+};
+
+static int rmax_bucket(int r) { return r <= 32 ? 32 : (r <= 64 ? 64 : 128); }
+
+template <typename T, int RMAX>
+static void launch_pass(Node* nodes, int count, int tiles, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass<T, RMAX>), dim3(tiles, count), dim3(kThreads), 0, s, nodes);
+}
+template <typename T, int RMAX>
+static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
+  hipLaunchKernelGGL((k_ctl<T, RMAX>), dim3(count), dim3(kThreads), 0, s, nodes, done, startup);
+}
+
+template <typename T>
+static void pass_any(int rb, Node* nodes, int count, int tiles, hipStream_t s) {
+  if (rb == 32) launch_pass<T, 32>(nodes, count, tiles, s);
+  else if (rb == 64) launch_pass<T, 64>(nodes, count, tiles, s);
+  else launch_pass<T, 128>(nodes, count, tiles, s);
+}
+template <typename T>
+static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
+  if (rb == 32) launch_ctl<T, 32>(nodes, count, done, startup, s);
+  else if (rb == 64) launch_ctl<T, 64>(nodes, count, done, startup, s);
+  else launch_ctl<T, 128>(nodes, count, done, startup, s);
+}
+
+// Runs pass/ctl iterations on one level until all `count` nodes are done.
+template <typename T>
+static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int tiles, int32_t* d_done,
+                            int64_t max_iters) {
+  hipStream_t s = ctx->stream;
+  volatile int32_t* h = ctx->host_flag;
+  hipEvent_t ev;
+  CUR_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  ctl_any<T>(rb, nodes, count, d_done, 1, s);  // start-up decisions
+  const int K = 4;
+  int64_t it = 0;
+  bool pending = false;
+  cur_status rc = CUR_OK;
+  for (;;) {
+    for (int j = 0; j < K; ++j) {
+      pass_any<T>(rb, nodes, count, tiles, s);
+      ctl_any<T>(rb, nodes, count, d_done, 0, s);
+    }
+    it += K;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(std::string("kernel launch: ") + hipGetErrorString(e));
+      rc = CUR_ERR_DEVICE;
+      break;
+    }
+    if (pending) {
+      e = hipEventSynchronize(ev);
+      if (e != hipSuccess) {
+        set_error(std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        rc = CUR_ERR_DEVICE;
+        break;
+      }
+      if (*h >= count) break;
+    }
+    e = hipMemcpyAsync((void*)h, d_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev, s);
+    if (e != hipSuccess) {
+      set_error(std::string("poll: ") + hipGetErrorString(e));
+      rc = CUR_ERR_DEVICE;
+      break;
+    }
+    pending = true;
+    if (it > max_iters) {
+      set_error("selection did not converge within the iteration bound");
+      rc = CUR_ERR_INTERNAL;
+      break;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(ev);
+  return rc;
+}
+
+template <typename T>
+static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
+                              const cur_opts& o, int64_t* I, int64_t* J, cur_info* info) {
+  hipStream_t s = ctx->stream;
+  const int w = o.col_block;
+  const double tau = o.tau;
+  const int smax = o.max_swaps;
+  const int rb = rmax_bucket(r);
+
+  // ---- a0: scan
+  double theta = 0.0;
+  {
+    cur_status ast = ensure_arena(ctx, 4096);
+    if (ast != CUR_OK) return ast;
+    unsigned long long* d = (unsigned long long*)ctx->arena;
+    CUR_HIP_CHECK(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), s));
+    const int blocks = (int)std::min<int64_t>(4096, (m * n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_amax<T>), dim3(std::max(blocks, 1)), dim3(kThreads), 0, s, A, m, n, lda, d);
+    unsigned long long hv[2];
+    CUR_HIP_CHECK(hipMemcpyAsync(hv, d, sizeof(hv), hipMemcpyDeviceToHost, s));
+    CUR_HIP_CHECK(hipStreamSynchronize(s));
+    if (hv[1]) {
+      set_error("A holds NaN or Inf");
+      return CUR_ERR_NONFINITE;
+    }
+    double amax;
+    std::memcpy(&amax, &hv[0], sizeof(double));
+    if (amax == 0.0) {
+      if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->logvol = -HUGE_VAL;
+      }
+      std::vector<int64_t> neg(r, -1);
+      CUR_HIP_CHECK(hipMemcpyAsync(I, neg.data(), r * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      CUR_HIP_CHECK(hipMemcpyAsync(J, neg.data(), r * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      CUR_HIP_CHECK(hipStreamSynchronize(s));
+      set_error("A is zero");
+      return CUR_ERR_RANK;
+    }
+    const double ulp = sizeof(T) == 8 ? 0x1p-52 : 0x1p-23;
+    theta = (double)std::max(m, n) * ulp * amax;
+  }
+
+  // ---- plan the tree
+  const int64_t b64 = std::max<int64_t>(1, n / w);
+  const int b = (int)b64;
+  std::vector<LevelPlan> levels;
+  int total = 0;
+  for (int c = b;;) {
+    levels.push_back({c, total});
+    total += c;
+    if (c <= 1) break;
+    c = (c + 1) / 2;
+  }
+  const int ntiles = (int)((m + kTileRows - 1) / kTileRows);
+  // candidate capacity of each level
+  std::vector<int> ncmax(levels.size());
+  int leafmax = 0;
+  for (int k = 0; k < b; ++k) {
+    const int64_t c0 = (int64_t)k * w, c1 = (k == b - 1) ? n : (int64_t)(k + 1) * w;
+    leafmax = std::max<int>(leafmax, (int)(c1 - c0));
+  }
+  ncmax[0] = leafmax;
+  for (size_t l = 1; l < levels.size(); ++l) ncmax[l] = 2 * r;
+
+  // ---- workspace layout
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t bytes = 4096;  // scan words + done counters
+  bytes += al(sizeof(Node) * total);
+  for (size_t l = 0; l < levels.size(); ++l) {
+    const int nc = ncmax[l];
+    const int wd = std::max(nc, r);
+    size_t per = 0;
+    per += al(sizeof(T) * m * nc);            // panel
+    per += al(sizeof(T) * m * wd);            // work
+    per += al(sizeof(double) * r * r);        // X
+    per += al(sizeof(double) * r * nc);       // Bc
+    per += al(sizeof(double) * (wd + 128 + nc));  // vec (w | rowk)
+    per += al(sizeof(Partial) * ntiles);
+    per += al(sizeof(double) * ntiles * wd);  // prow
+    per += al(sizeof(int64_t) * nc);          // Jc
+    per += al(sizeof(int32_t) * nc) * 2;      // colmap, srcpos
+    per += al(nc);                            // insel
+    per += al(sizeof(int64_t) * r) + al(sizeof(int32_t) * r);
+    bytes += per * levels[l].count;
+  }
+  bytes += al(sizeof(int64_t) * b);  // leaf col0
+  bytes += al(sizeof(int64_t) * 2 * (size_t)total * r);  // export buffers
+  cur_status st = ensure_arena(ctx, bytes);
+  if (st != CUR_OK) return st;
+  Arena ar{(char*)ctx->arena, ctx->arena_bytes, 0};
+  int32_t* d_done = (int32_t*)ar.take(4096);
+  Node* d_nodes = (Node*)ar.take(sizeof(Node) * total);
+  std::vector<Node> h(total);
+  std::memset(h.data(), 0, sizeof(Node) * total);
+  for (size_t l = 0; l < levels.size(); ++l) {
+    const int nc = ncmax[l];
+    const int wd = std::max(nc, r);
+    for (int k = 0; k < levels[l].count; ++k) {
+      Node& nd = h[levels[l].first + k];
+      nd.m = m;
+      nd.r = r;
+      nd.ncmax = nc;
+      nd.ntiles = ntiles;
+      nd.smax = smax;
+      nd.tau = tau;
+      nd.theta = theta;
+      nd.panel = ar.take(sizeof(T) * m * nc);
+      nd.work = ar.take(sizeof(T) * m * wd);
+      nd.X = (double*)ar.take(sizeof(double) * r * r);
+      nd.Bc = (double*)ar.take(sizeof(double) * r * nc);
+      nd.vec = (double*)ar.take(sizeof(double) * (wd + 128 + nc));
+      nd.part = (Partial*)ar.take(sizeof(Partial) * ntiles);
+      nd.prow = (double*)ar.take(sizeof(double) * ntiles * wd);
+      nd.Jc = (int64_t*)ar.take(sizeof(int64_t) * nc);
+      nd.colmap = (int32_t*)ar.take(sizeof(int32_t) * nc);
+      nd.srcpos = (int32_t*)ar.take(sizeof(int32_t) * nc);
+      nd.insel = (uint8_t*)ar.take(nc);
+      nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
+      nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
+      if (!nd.panel || !nd.work || !nd.insel || !nd.Jp) {
+        set_error("workspace layout overflow");
+        return CUR_ERR_INTERNAL;
+      }
+      if (l == 0) {
+        const int64_t c0 = (int64_t)k * w, c1 = (k == b - 1) ? n : (int64_t)(k + 1) * w;
+        nd.kind = KIND_LEAF;
+        nd.child0 = nd.child1 = -1;
+        nd.nc = (int)(c1 - c0);
+        nd.st = ST_ACA;
+        nd.t = 0;
+        nd.na = nd.nc;
+        nd.steps = (int)std::min<int64_t>(std::min<int64_t>(r, nd.nc), m);
+      } else {
+        const int pc = levels[l - 1].count;
+        if (2 * k + 1 < pc) {
+          nd.kind = KIND_MERGE;
+          nd.child0 = 2 * k;
+          nd.child1 = 2 * k + 1;
+        } else {
+          nd.kind = KIND_PROMOTED;
+          nd.child0 = 2 * k;
+          nd.child1 = -1;
+          const Node& c = h[levels[l - 1].first + 2 * k];
+          nd.panel = c.panel;
+          nd.Jc = c.Jc;
+          nd.ncmax = c.ncmax;
+        }
+        nd.st = ST_DONE;
+      }
+    }
+  }
+  int64_t* d_col0 = (int64_t*)ar.take(sizeof(int64_t) * b);
+  int64_t* d_expI = (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * r);
+  int64_t* d_expJ = (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * r);
+  std::vector<int64_t> col0(b);
+  for (int k = 0; k < b; ++k) col0[k] = (int64_t)k * w;
+  CUR_HIP_CHECK(hipMemcpyAsync(d_col0, col0.data(), sizeof(int64_t) * b, hipMemcpyHostToDevice, s));
+  CUR_HIP_CHECK(hipMemcpyAsync(d_nodes, h.data(), sizeof(Node) * total, hipMemcpyHostToDevice, s));
+  CUR_HIP_CHECK(hipMemsetAsync(d_done, 0, 4096, s));
+
+  // ---- level 0
+  Node* L0 = d_nodes;
+  hipLaunchKernelGGL(k_leaf_init, dim3(b), dim3(kThreads), 0, s, L0, d_col0);
+  hipLaunchKernelGGL((k_panel_from_A<T>), dim3((m + kTR - 1) / kTR, (leafmax + 63) / 64, b),
+                     dim3(kThreads), 0, s, L0, A, lda, d_col0);
+  const int64_t iter_bound = 16 * (int64_t)(r + 4) + 8 * (int64_t)smax + 4096;
+  cur_status rc = run_level<T>(ctx, rb, L0, b, ntiles, d_done + 0, iter_bound);
+  if (rc != CUR_OK) return rc;
+
+  // ---- merges
+  for (size_t l = 1; l < levels.size(); ++l) {
+    Node* cur = d_nodes + levels[l].first;
+    Node* prev = d_nodes + levels[l - 1].first;
+    const int cnt = levels[l].count;
+    int32_t* dd = d_done + 16 * (int)l;
+    hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev, dd);
+    const int gx = (int)std::min<int64_t>((m + kThreads - 1) / kThreads, 64);
+    hipLaunchKernelGGL((k_panel_build<T>), dim3(gx, 2 * r, cnt), dim3(kThreads), 0, s, cur, prev);
+    rc = run_level<T>(ctx, rb, cur, cnt, ntiles, dd, iter_bound);
+    if (rc != CUR_OK) return rc;
+  }
+
+  // ---- outputs
+  const Node* d_root = d_nodes + levels.back().first;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, d_root, I, J);
+  CUR_HIP_CHECK(hipMemcpyAsync(h.data(), d_nodes, sizeof(Node) * total, hipMemcpyDeviceToHost, s));
+  cur_trace* tr = o.trace;
+  std::vector<int64_t> eI, eJ;
+  if (tr) {
+    hipLaunchKernelGGL(k_export, dim3(total), dim3(kThreads), 0, s, d_nodes, d_expI, d_expJ, r);
+    eI.resize((size_t)total * r);
+    eJ.resize((size_t)total * r);
+    CUR_HIP_CHECK(hipMemcpyAsync(eI.data(), d_expI, sizeof(int64_t) * eI.size(), hipMemcpyDeviceToHost, s));
+    CUR_HIP_CHECK(hipMemcpyAsync(eJ.data(), d_expJ, sizeof(int64_t) * eJ.size(), hipMemcpyDeviceToHost, s));
+  }
+  CUR_HIP_CHECK(hipStreamSynchronize(s));
+
+  cur_status result = CUR_OK;
+  int32_t nodes = 0, phases = 0, refreshes = 0;
+  int64_t swaps = 0;
+  bool nocap = false;
+  for (size_t l = 0; l < levels.size(); ++l)
+    for (int k = 0; k < levels[l].count; ++k) {
+      const Node& nd = h[levels[l].first + k];
+      if (nd.err) result = CUR_ERR_INTERNAL;
+      if (nd.kind == KIND_PROMOTED) continue;
+      nodes++;
+      phases += nd.phases;
+      refreshes += nd.refreshes;
+      swaps += nd.swaps;
+      nocap |= nd.nocap != 0;
+    }
+  const Node& root = h[levels.back().first];
+  if (result == CUR_OK) {
+    if (root.is_short) {
+      result = CUR_ERR_RANK;
+      set_error("rank-short: fewer than r pivots above the threshold");
+    } else if (nocap) {
+      result = CUR_WARN_NOCONV;
+    }
+  } else {
+    set_error("singular cross met inside the swap loop");
+  }
+  if (info) {
+    info->rank = root.q;
+    info->nodes = nodes;
+    info->phases = phases;
+    info->refreshes = refreshes;
+    info->swaps = swaps;
+    info->logvol = root.is_short ? -HUGE_VAL : std::log(root.vol_m) + root.vol_e * 0.69314718055994530942;
+  }
+  if (tr) {
+    const int cap = tr->capacity;
+    int slot = 0;
+    for (size_t l = 0; l < levels.size(); ++l)
+      for (int k = 0; k < levels[l].count; ++k, ++slot) {
+        if (slot >= cap) continue;
+        const Node& nd = h[levels[l].first + k];
+        int64_t* mt = tr->meta + (size_t)slot * kMetaFields;
+        const bool pr = nd.kind == KIND_PROMOTED;
+        mt[0] = (int64_t)l;
+        mt[1] = k;
+        mt[2] = nd.q;
+        mt[3] = nd.is_short;
+        mt[4] = pr ? 1 : 0;
+        mt[5] = pr ? 0 : nd.nocap;
+        mt[6] = pr ? 0 : nd.swaps;
+        mt[7] = pr ? 0 : nd.phases;
+        mt[8] = pr ? 0 : nd.refreshes;
+        mt[9] = nd.is_short ? 0 : nd.vol_e;
+        tr->vol_mant[slot] = nd.is_short ? 0.0 : nd.vol_m;
+        for (int j = 0; j < r; ++j) {
+          tr->I[(size_t)slot * r + j] = eI[(size_t)(levels[l].first + k) * r + j];
+          tr->J[(size_t)slot * r + j] = eJ[(size_t)(levels[l].first + k) * r + j];
+        }
+      }
+    tr->count = total;
+  }
+  return result;
+}
+
+cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
+                           int64_t lda, int r, const cur_opts& o, int64_t* I, int64_t* J,
+                           cur_info* info) {
+  if (dtype == CUR_F64)
+    return select_impl<double>(ctx, (const double*)A, m, n, lda, r, o, I, J, info);
+  return select_impl<float>(ctx, (const float*)A, m, n, lda, r, o, I, J, info);
+}
+
+}  // namespace cur

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+FP64 path: index sets, statuses and every per-node counter of the selection
+tree must equal the oracle's exactly; the volumes agree to rounding of log.
+FP32 path: any dominant result is acceptable; its volume ratio to the oracle's
+FP64 selection on the exactly upcast input must be >= 0.99.
+Assembly: C and R are gathers (bit-exact); U is bit-exact when the LU inverse
+is used.  Residual: |cheb_gpu - cheb_oracle| <= 1e-10 ||A||_C and the same
+bound for the Frobenius relative error (rounding of an r-term dot product with
+|B| <= 1 is ~ r eps ||A||_C, far below it).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2502_11017_amd as cur  # noqa: E402
+from paper_2502_11017_amd import workloads as W  # noqa: E402
+from tests.helpers import row_interp  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_both(orc, A, r, w=0, tau=0.0, max_swaps=0):
+    Ah = A.detach().cpu().numpy()
+    say(f"case m={Ah.shape[0]} n={Ah.shape[1]} r={r} w={w} dtype={A.dtype}")
+    g = cur.select(A, r, col_block=w, tau=tau, max_swaps=max_swaps, trace=True)
+    o = orc.select(Ah, r, w=w, tau=tau, max_swaps=max_swaps, trace=True)
+    return g, o, Ah
+
+
+def assert_same_selection(g, o):
+    gI, gJ = g["I"].cpu().numpy(), g["J"].cpu().numpy()
+    assert g["status"] == o["status"], (g["status"], o["status"])
+    assert g["rank"] == o["rank"]
+    np.testing.assert_array_equal(gI, o["I"])
+    np.testing.assert_array_equal(gJ, o["J"])
+    for key in ("nodes", "phases", "refreshes", "swaps"):
+        assert g[key] == o[key], (key, g[key], o[key])
+    gt, ot = g["trace"], o["trace"]
+    np.testing.assert_array_equal(gt["meta"], ot["meta"])
+    np.testing.assert_array_equal(gt["I"], ot["I"])
+    np.testing.assert_array_equal(gt["J"], ot["J"])
+    np.testing.assert_array_equal(gt["vol_m"], ot["vol_m"])  # same rounded products
+    if np.isfinite(o["logvol"]):
+        assert abs(g["logvol"] - o["logvol"]) <= 1e-12 * max(1.0, abs(o["logvol"]))
+
+
+CASES_F64 = [
+    # (m, n, r, w, seed): several tiles, ragged tails, odd node counts
+    (200, 300, 8, 16, 1),
+    (300, 1000, 5, 64, 2),     # last block takes the remainder (1000 = 15*64 + 40)
+    (513, 700, 16, 32, 3),     # m not a multiple of the 256-row tile
+    (1000, 97, 3, 3, 4),       # 32 leaves of width 3, last one 4
+    (64, 64, 64, 64, 5),       # r = min(m, n): single leaf, full cross
+    (777, 129, 1, 0, 6),       # r = 1
+    (260, 2048, 32, 32, 7),    # 64 leaves
+    (2000, 640, 96, 128, 8),   # r in the 128 bucket
+]
+
+
+@pytest.mark.parametrize("m,n,r,w,seed", CASES_F64)
+def test_select_f64_matches_oracle(orc, m, n, r, w, seed):
+    A = torch.from_numpy(W.gaussian(m, n, seed)).to(DEV)
+    g, o, _ = run_both(orc, A, r, w)
+    assert_same_selection(g, o)
+
+
+def test_select_f64_c1(orc):
+    A = W.c1(1).to(DEV)
+    g, o, Ah = run_both(orc, A, 16)
+    assert g["status"] == 0
+    assert_same_selection(g, o)
+    assert np.abs(row_interp(Ah, o["I"], o["J"])).max() <= 1 + 1e-12
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_select_f64_c2_recipe_small(orc, n):
+    # the C2 construction (geometric 0.9 spectrum, 1e-6 floor, 1e-7 noise) at reduced size
+    A = W.c2(20 + n, device=DEV, n=n)
+    g, o, _ = run_both(orc, A, 64)
+    assert_same_selection(g, o)
+
+
+def test_select_f64_rank_short(orc):
+    rng = np.random.default_rng(9)
+    A = torch.from_numpy(rng.standard_normal((300, 3)) @ rng.standard_normal((3, 400))).to(DEV)
+    g, o, _ = run_both(orc, A, 6, 32)
+    assert o["status"] == orc.ERR_RANK
+    assert_same_selection(g, o)
+
+
+def test_select_f64_noconv(orc):
+    A = torch.from_numpy(W.gaussian(300, 256, 10)).to(DEV)
+    g, o, _ = run_both(orc, A, 8, 16, max_swaps=1)
+    assert o["status"] == orc.WARN_NOCONV
+    assert_same_selection(g, o)
+
+
+def test_select_hilbert_and_recip(orc):
+    A = torch.from_numpy(W.hilbert(256)).to(DEV)
+    g, o, _ = run_both(orc, A, 6)
+    assert_same_selection(g, o)
+    A = torch.from_numpy(W.recip_lowrank(512, 20)).to(DEV)
+    g, o, _ = run_both(orc, A, 20)
+    assert o["status"] == orc.ERR_RANK
+    assert_same_selection(g, o)
+
+
+def test_select_errors():
+    say("case error paths")
+    A = torch.zeros((40, 50), dtype=torch.float64, device=DEV)
+    g = cur.select(A, 3)
+    assert g["status"] == cur.ERR_RANK and g["rank"] == 0
+    assert (g["I"].cpu() == -1).all()
+    A = torch.from_numpy(W.gaussian(40, 50, 1)).to(DEV)
+    A[3, 7] = float("nan")
+    with pytest.raises(cur.CurError) as ei:
+        cur.select(A, 3)
+    assert ei.value.status == cur.ERR_NONFINITE
+    with pytest.raises(cur.CurError) as ei:
+        cur.select(A, 0)
+    assert ei.value.status == cur.ERR_ARG
+    with pytest.raises(cur.CurError) as ei:
+        cur.select(A, 5, col_block=4)
+    assert ei.value.status == cur.ERR_ARG
+
+
+@pytest.mark.parametrize("m,n,r,w,seed", [(400, 600, 12, 32, 11), (1500, 900, 40, 64, 12)])
+def test_select_f32_volume_ratio(orc, m, n, r, w, seed):
+    A64 = W.c2(seed, n=max(m, n))[:m, :n].contiguous()
+    A = A64.to(torch.float32).to(DEV)
+    Ah = A.cpu().numpy().astype(np.float64)
+    say(f"case f32 m={m} n={n} r={r} w={w}")
+    g = cur.select(A, r, col_block=w)
+    o = orc.select(Ah, r, w=w)
+    assert g["status"] in (cur.OK, cur.WARN_NOCONV)
+    gI, gJ = g["I"].cpu().numpy(), g["J"].cpu().numpy()
+    assert len(set(gI)) == r and len(set(gJ)) == r
+    ratio = np.exp(orc.logvol(Ah, gI, gJ) - orc.logvol(Ah, o["I"], o["J"]))
+    say(f"  volume ratio {ratio:.6f}")
+    assert ratio >= 0.99
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_assemble_and_residual_match_oracle(orc, dtype):
+    A = W.c1(1).to(dtype).to(DEV)
+    Ah = A.cpu().numpy().astype(np.float64)
+    o = orc.select(Ah, 16)
+    I = torch.from_numpy(o["I"]).to(DEV)
+    J = torch.from_numpy(o["J"]).to(DEV)
+    say(f"case assemble/residual c1 {dtype}")
+    C, U, R = cur.assemble(A, I, J)
+    oC, oU, oR, used = orc.assemble(Ah, o["I"], o["J"])
+    assert not used
+    np.testing.assert_array_equal(C.cpu().numpy().astype(np.float64), oC)
+    np.testing.assert_array_equal(R.cpu().numpy().astype(np.float64), oR)
+    np.testing.assert_array_equal(U.cpu().numpy(), oU)
+    cheb, fro = cur.residual(A, C, U, R)
+    ocheb, ofro = orc.residual(Ah, oC, oU, oR)
+    amax = np.abs(Ah).max()
+    assert abs(cheb - ocheb) <= 1e-10 * amax
+    assert abs(fro - ofro) <= 1e-10
+
+
+def test_assemble_pinv_branch(orc):
+    # a repeated column makes A(I,J) singular: the pseudo-inverse branch
+    rng = np.random.default_rng(5)
+    Ah = rng.standard_normal((30, 20))
+    Ah[:, 7] = Ah[:, 3]
+    I = np.array([1, 4, 9, 16])
+    J = np.array([2, 3, 7, 11])
+    A = torch.from_numpy(Ah).to(DEV)
+    say("case assemble pinv")
+    C, U, R = cur.assemble(A, torch.from_numpy(I).to(DEV), torch.from_numpy(J).to(DEV))
+    _, oU, _, used = orc.assemble(Ah, I, J)
+    assert used
+    np.testing.assert_allclose(U.cpu().numpy(), oU, rtol=0, atol=1e-10 * np.abs(oU).max())
+
+
+@pytest.mark.parametrize("m,n,r", [(1000, 700, 24), (3000, 257, 100)])
+def test_residual_ragged(orc, m, n, r):
+    Ah = W.gaussian(m, r, 3) @ W.gaussian(r, n, 4) + 1e-3 * W.gaussian(m, n, 5)
+    A = torch.from_numpy(Ah).to(DEV)
+    rng = np.random.default_rng(6)
+    I = np.sort(rng.choice(m, r, replace=False))
+    J = np.sort(rng.choice(n, r, replace=False))
+    say(f"case residual m={m} n={n} r={r}")
+    C, U, R = cur.assemble(A, torch.from_numpy(I).to(DEV), torch.from_numpy(J).to(DEV))
+    cheb, fro = cur.residual(A, C, U, R)
+    oC, oU, oR, _ = orc.assemble(Ah, I, J)
+    ocheb, ofro = orc.residual(Ah, oC, oU, oR)
+    amax = np.abs(Ah).max()
+    assert abs(cheb - ocheb) <= 1e-10 * amax
+    assert abs(fro - ofro) <= 1e-10
+
+
+def test_select_batched_matches_single(orc):
+    say("case batched")
+    As = [torch.from_numpy(W.gaussian(m, n, s)).to(DEV) for (m, n, s) in [(300, 200, 1), (128, 500, 2), (700, 64, 3)]]
+    rs = [8, 16, 4]
+    outs, rc = cur.select_batched(As, rs)
+    assert rc == cur.OK
+    for (I, J, st), A, r in zip(outs, As, rs):
+        o = orc.select(A.cpu().numpy(), r)
+        assert st == o["status"]
+        np.testing.assert_array_equal(I.cpu().numpy(), o["I"])
+        np.testing.assert_array_equal(J.cpu().numpy(), o["J"])
