@@ -99,8 +99,9 @@ typedef struct {
 void cur_opts_init(cur_opts* opts);
 
 /* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is
- * used for all work; NULL creates and owns a stream of the default priority.
- * The context owns a device workspace that grows on demand. */
+ * used for all work; NULL means the device's default (null) stream, so work is
+ * ordered with everything else issued there.  The context owns a device
+ * workspace that grows on demand. */
 cur_status cur_create(cur_ctx* out, int device, void* hip_stream);
 cur_status cur_destroy(cur_ctx ctx);
 const char* cur_strerror(cur_status s);
@@ -165,6 +166,24 @@ typedef struct {
  */
 cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items, const cur_opts* opts,
                               cur_status* per_item);
+
+/* Measurement counters of the selection's row passes (the bandwidth-bound
+ * sweeps: ACA rank-1 updates, fresh interpolation matrices, Sherman-Morrison
+ * row swaps).  While enabled, cur_select brackets every pass launch with HIP
+ * events on the context's stream and counts on the device the algorithmic
+ * bytes each pass must move (every element of the working columns it reads
+ * plus every element it writes, once). */
+typedef struct {
+  int64_t launches;   /* pass launches timed                                   */
+  int64_t busy;       /* launches in which at least one node had work          */
+  double seconds;     /* summed event time of those launches                   */
+  double bytes;       /* summed algorithmic bytes                              */
+} cur_profile;
+
+/* Enable (1) or disable (0) the counters; enabling clears them. */
+cur_status cur_profile_enable(cur_ctx ctx, int enable);
+/* Copy the counters accumulated since enabling (host struct). */
+cur_status cur_profile_read(cur_ctx ctx, cur_profile* out);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,8 @@ TRACE_FIELDS = ("level", "index", "q", "short", "promoted", "nocap", "swaps", "p
                 "refreshes", "vol_e")
 
 EXPORTS = ("cur_opts_init", "cur_create", "cur_destroy", "cur_strerror", "cur_last_error",
-           "cur_select", "cur_assemble", "cur_residual", "cur_select_batched")
+           "cur_select", "cur_assemble", "cur_residual", "cur_select_batched",
+           "cur_profile_enable", "cur_profile_read")
 
 
 class CurError(RuntimeError):
@@ -54,6 +55,11 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int32), ("nodes", ctypes.c_int32), ("phases", ctypes.c_int32),
                 ("refreshes", ctypes.c_int32), ("swaps", ctypes.c_int64), ("logvol", ctypes.c_double)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("busy", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class Item(ctypes.Structure):
@@ -95,6 +101,10 @@ def lib():
         L.cur_select_batched.argtypes = [P, i32, ctypes.POINTER(Item), ctypes.POINTER(Opts),
                                          ctypes.POINTER(ctypes.c_int)]
         L.cur_select_batched.restype = ctypes.c_int
+        L.cur_profile_enable.argtypes = [P, ctypes.c_int]
+        L.cur_profile_enable.restype = ctypes.c_int
+        L.cur_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
+        L.cur_profile_read.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -239,6 +249,17 @@ def residual(A, C, U, R, prec: int = PREC_NATIVE):
                             ctypes.c_void_p(R.data_ptr()), int(prec), ctypes.byref(cheb), ctypes.byref(fro))
     _check(rc)
     return cheb.value, fro.value
+
+
+def profile_enable(enable: bool = True, device=None):
+    """Turn the pass timing / algorithmic-byte counters on (cleared) or off."""
+    _check(lib().cur_profile_enable(context(device), 1 if enable else 0))
+
+
+def profile_read(device=None) -> dict:
+    p = Profile()
+    _check(lib().cur_profile_read(context(device), ctypes.byref(p)))
+    return {"launches": p.launches, "seconds": p.seconds, "bytes": p.bytes}
 
 
 def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0):

@@ -137,18 +137,12 @@ cur_status cur_create(cur_ctx* out, int device, void* hip_stream) {
   c->arena = nullptr;
   c->arena_bytes = 0;
   c->last_pinv = 0;
-  if (hip_stream) {
-    c->stream = (hipStream_t)hip_stream;
-    c->own_stream = false;
-  } else {
-    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      delete c;
-      set_error(std::string("hipStreamCreate: ") + hipGetErrorString(e));
-      return CUR_ERR_DEVICE;
-    }
-    c->own_stream = true;
-  }
+  c->prof_on = 0;
+  c->prof_bytes = nullptr;
+  c->prof_ev = new std::vector<hipEvent_t>();
+  std::memset(&c->prof, 0, sizeof(c->prof));
+  c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
+  c->own_stream = false;
   e = hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault);
   if (e != hipSuccess) {
     if (c->own_stream) hipStreamDestroy(c->stream);
@@ -170,6 +164,9 @@ cur_status cur_destroy(cur_ctx ctx) {
   if (ctx->arena) hipFree(ctx->arena);
   if (ctx->host_flag) hipHostFree(ctx->host_flag);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  if (ctx->prof_bytes) hipFree(ctx->prof_bytes);
+  for (hipEvent_t e : *ctx->prof_ev) hipEventDestroy(e);
+  delete ctx->prof_ev;
   delete ctx;
   return CUR_OK;
 }
@@ -219,6 +216,31 @@ cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, 
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
   return residual_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
+}
+
+cur_status cur_profile_enable(cur_ctx ctx, int enable) {
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  if (enable && !ctx->prof_bytes) CUR_HIP_CHECK(hipMalloc((void**)&ctx->prof_bytes, 64));
+  if (enable) {
+    CUR_HIP_CHECK(hipMemsetAsync(ctx->prof_bytes, 0, 64, ctx->stream));
+    CUR_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  }
+  std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+  ctx->prof_on = enable ? 1 : 0;
+  return CUR_OK;
+}
+
+cur_status cur_profile_read(cur_ctx ctx, cur_profile* out) {
+  if (!ctx || !out) return arg_error("ctx and out must be non-NULL");
+  *out = ctx->prof;
+  if (ctx->prof_bytes) {
+    unsigned long long b = 0;
+    CUR_HIP_CHECK(hipMemcpyAsync(&b, ctx->prof_bytes, sizeof(b), hipMemcpyDeviceToHost, ctx->stream));
+    CUR_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    out->bytes = (double)b;
+  }
+  return CUR_OK;
 }
 
 cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items, const cur_opts* opts,

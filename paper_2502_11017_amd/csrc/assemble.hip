@@ -57,13 +57,13 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
     L.A[idx] = (double)A[I[a] * lda + J[b]];
   }
   __syncthreads();
-  const bool ok = block_gepp(L.A, r, L.perm, L.lk, &L.spiv);
+  const bool ok = block_gepp(L.A, r, L.perm, &L.spiv);
   if (tid == 0) {
     int use_pinv = 1;
     if (ok) {
       double umin = HUGE_VAL, umax = 0.0;
       for (int k = 0; k < r; ++k) {
-        const double u = fabs(L.A[k * r + k]);
+        const double u = fabs(L.A[L.perm[k] * r + k]);
         umin = fmin(umin, u);
         umax = fmax(umax, u);
       }
@@ -74,7 +74,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
   }
   __syncthreads();
   if (!L.pinv) {
-    block_lu_inverse(L.A, L.perm, r, L.B, AsmLds<RMAX>::CH, U);
+    if constexpr (RMAX <= 64)
+      block_lu_inverse_reg<RMAX>(L.A, L.perm, r, L.B, U);
+    else
+      block_lu_inverse(L.A, L.perm, r, L.B, AsmLds<RMAX>::CH, U);
     return;
   }
   // ---- one-sided Jacobi: W = G V with orthogonal columns (cyclic pairs, <= 60 sweeps)
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
     W[idx] = (double)A[I[a] * lda + J[b]];
     V[idx] = (a == b) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  block_global_sync();
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) L.rot = 0;
     __syncthreads();
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
             V[i * r + q] = s * vp + c * vq;
           }
         }
-        __syncthreads();
+        block_global_sync();
       }
     if (!L.rot) break;
   }
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
     }
     L.cs[0] = (double)r * 0x1p-52 * smax;
   }
-  __syncthreads();
+  block_global_sync();
   const double cut = L.cs[0];
   for (int idx = tid; idx < r * r; idx += kThreads) {
     const int a = idx / r, b = idx % r;

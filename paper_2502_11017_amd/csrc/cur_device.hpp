@@ -71,88 +71,102 @@ __device__ __forceinline__ Cand block_argmax(Cand c, Cand* sc) {
   return b;
 }
 
-// ---------------------------------------------------------------- small dense kernels
-// LU with partial pivoting of the r x r row-major G held in LDS, in place.
-// Pivot of column k: largest |G(a,k)| over a >= k, ties to the smallest a.
-// perm[k] receives the original row now at position k.  lk: r doubles of LDS;
-// spiv: one int of LDS.  Returns false (uniformly) if G is singular.
-__device__ bool block_gepp(double* G, int r, int* perm, double* lk, int* spiv) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < r; i += nt) perm[i] = i;
+// Make the block's global-memory stores visible to every thread of the block.
+// A workgroup barrier orders LDS but not the global stores of other
+// wavefronts, so each thread first completes and publishes its own stores
+// (agent-scope fence: waits for them and drops stale vector-L1 lines), then
+// the block synchronizes.  Used only where one wavefront reads global data
+// that another wavefront of the same block wrote in the same launch.
+__device__ __forceinline__ void block_global_sync() {
+  __threadfence();
   __syncthreads();
+}
+
+// ---------------------------------------------------------------- small dense kernels
+// LU with partial pivoting of the r x r row-major G held in LDS, in place and
+// without moving rows: rowmap[p] is the LDS row that holds position p (rows
+// stay where they were loaded, so rowmap[p] is also the original row of
+// position p).  The arithmetic is exactly that of swapping rows: pivot of
+// column k = largest |G(p,k)| over positions p >= k, ties to the smallest p;
+// multiplier l = G(p,k) / G(k,k) stored in place; G(p,c) = fma(-l, G(k,c), G(p,c)).
+// Each row is updated by a group of lanes of one wavefront, which makes the
+// in-place store of l race-free.  spiv: one int of LDS.  Returns false
+// (uniformly) if G is singular.
+__device__ bool block_gepp(double* G, int r, int* rowmap, int* spiv) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int i = tid; i < r; i += blockDim.x) rowmap[i] = i;
+  __syncthreads();
+  constexpr int LPR = 16;             // lanes per row
+  const int rpw = 64 / LPR;           // rows per wavefront per round
+  const int grp = lane / LPR, sub = lane % LPR;
   for (int k = 0; k < r; ++k) {
-    if (tid < 64) {
+    if (wave == 0) {
       double best = -1.0;
       int arg = r;
-      for (int a = k + tid; a < r; a += 64) {
-        double v = fabs(G[a * r + k]);
-        if (v > best) { best = v; arg = a; }
+      for (int p = k + lane; p < r; p += 64) {
+        const double v = fabs(G[rowmap[p] * r + k]);
+        if (v > best) { best = v; arg = p; }
       }
 #pragma unroll
       for (int s = 32; s >= 1; s >>= 1) {
-        double ob = __shfl_xor(best, s, 64);
-        int oa = __shfl_xor(arg, s, 64);
+        const double ob = __shfl_xor(best, s, 64);
+        const int oa = __shfl_xor(arg, s, 64);
         if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
       }
-      if (tid == 0) *spiv = (best == 0.0) ? -1 : arg;
-    }
-    __syncthreads();
-    const int piv = *spiv;
-    if (piv < 0) return false;
-    if (piv != k) {
-      for (int c = tid; c < r; c += nt) {
-        double t = G[k * r + c];
-        G[k * r + c] = G[piv * r + c];
-        G[piv * r + c] = t;
-      }
-      if (tid == 0) {
-        int t = perm[k];
-        perm[k] = perm[piv];
-        perm[piv] = t;
+      if (lane == 0) {
+        if (best == 0.0) {
+          *spiv = -1;
+        } else {
+          *spiv = arg;
+          const int t = rowmap[k];
+          rowmap[k] = rowmap[arg];
+          rowmap[arg] = t;
+        }
       }
     }
     __syncthreads();
-    const double d = G[k * r + k];
-    for (int a = k + 1 + tid; a < r; a += nt) lk[a] = G[a * r + k] / d;
-    __syncthreads();
-    const int cols = r - k, rows = r - k - 1;
-    for (int idx = tid; idx < rows * cols; idx += nt) {
-      const int a = k + 1 + idx / cols, c = k + idx % cols;
-      if (c == k)
-        G[a * r + k] = lk[a];
-      else
-        G[a * r + c] = fma(-lk[a], G[k * r + c], G[a * r + c]);
+    if (*spiv < 0) return false;
+    const int pr = rowmap[k];
+    const double d = G[pr * r + k];
+    for (int p0 = k + 1 + wave * rpw; p0 < r; p0 += nw * rpw) {
+      const int p = p0 + grp;
+      if (p < r) {
+        const int ph = rowmap[p];
+        const double l = G[ph * r + k] / d;
+        for (int c = k + 1 + sub; c < r; c += LPR) G[ph * r + c] = fma(-l, G[pr * r + c], G[ph * r + c]);
+        if (sub == 0) G[ph * r + k] = l;
+      }
     }
     __syncthreads();
   }
   return true;
 }
 
-// X = G^{-1} (row-major r x r, written to global Xg) from the factors of
-// block_gepp, column chunk by column chunk in the LDS buffer Y (r x ch):
+// X = G^{-1} (row-major r x r, written to Xg: global or LDS) from the factors
+// of block_gepp, column chunk by column chunk in the LDS buffer Y (r x ch):
 // forward substitution L y = P e_j with the sum over k ascending, then back
 // substitution U x = y with the sum over k descending and x_k = s / U(k,k).
 // Each element receives its updates in exactly that order.
-__device__ void block_lu_inverse(const double* LU, const int* perm, int r, double* Y, int ch,
+__device__ void block_lu_inverse(const double* LU, const int* rowmap, int r, double* Y, int ch,
                                  double* Xg) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int j0 = 0; j0 < r; j0 += ch) {
     const int nch = min(ch, r - j0);
     for (int idx = tid; idx < r * nch; idx += nt) {
       const int i = idx / nch, jj = idx % nch;
-      Y[i * ch + jj] = (perm[i] == j0 + jj) ? 1.0 : 0.0;
+      Y[i * ch + jj] = (rowmap[i] == j0 + jj) ? 1.0 : 0.0;
     }
     __syncthreads();
     for (int k = 0; k < r - 1; ++k) {
       const int rows = r - k - 1;
       for (int idx = tid; idx < rows * nch; idx += nt) {
         const int i = k + 1 + idx / nch, jj = idx % nch;
-        Y[i * ch + jj] = fma(-LU[i * r + k], Y[k * ch + jj], Y[i * ch + jj]);
+        Y[i * ch + jj] = fma(-LU[rowmap[i] * r + k], Y[k * ch + jj], Y[i * ch + jj]);
       }
       __syncthreads();
     }
     for (int k = r - 1; k >= 0; --k) {
-      const double ukk = LU[k * r + k];
+      const double ukk = LU[rowmap[k] * r + k];
       // x_k is final once every U(k, k') (k' > k) term has been applied.
       for (int idx = tid; idx < (k + 1) * nch; idx += nt) {
         const int i = idx / nch, jj = idx % nch;
@@ -160,21 +174,68 @@ __device__ void block_lu_inverse(const double* LU, const int* perm, int r, doubl
         if (i == k)
           Xg[(int64_t)k * r + j0 + jj] = xk;
         else
-          Y[i * ch + jj] = fma(-LU[i * r + k], xk, Y[i * ch + jj]);
+          Y[i * ch + jj] = fma(-LU[rowmap[i] * r + k], xk, Y[i * ch + jj]);
       }
       __syncthreads();
     }
   }
 }
 
+// The same inverse with one thread per column j and the column held in
+// registers (r <= RMAX <= 64): forward substitution y_i = [rowmap[i] == j] -
+// sum_{k<i} L(i,k) y_k (k ascending), then back substitution
+// x_i = (y_i - sum_{k>i} U(i,k) x_k) / U(i,i) with k descending from r-1 --
+// the per-element operation order of block_lu_inverse, without barriers.
+// LUp: LDS scratch of RMAX*RMAX doubles (position-ordered copy of the factors).
+template <int RMAX>
+__device__ void block_lu_inverse_reg(const double* LU, const int* rowmap, int r, double* LUp,
+                                     double* Xg, double* Xl = nullptr) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < r * r; idx += blockDim.x) {
+    const int i = idx / r, k = idx % r;
+    LUp[i * RMAX + k] = LU[rowmap[i] * r + k];
+  }
+  __syncthreads();
+  const int j = tid;
+  if (j < r) {
+    double y[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) {
+      if (i < r) {
+        double s = (rowmap[i] == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) s = fma(-LUp[i * RMAX + k], y[k], s);
+        y[i] = s;
+      }
+    }
+#pragma unroll
+    for (int i = RMAX - 1; i >= 0; --i) {
+      if (i < r) {
+        double s = y[i];
+#pragma unroll
+        for (int k = RMAX - 1; k > i; --k)
+          if (k < r) s = fma(-LUp[i * RMAX + k], y[k], s);
+        y[i] = s / LUp[i * RMAX + i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < r) {
+        Xg[(int64_t)i * r + j] = y[i];
+        if (Xl) Xl[i * r + j] = y[i];
+      }
+  }
+  __syncthreads();
+}
+
 // |det| = prod |U(k,k)| as mant * 2^expo, mant in [0.5,1): frexp split of each
 // factor, one rounded product per step, exact renormalisation.  Thread 0 only.
-__device__ void lu_volume(const double* LU, int r, double* mant, int* expo) {
+__device__ void lu_volume(const double* LU, const int* rowmap, int r, double* mant, int* expo) {
   double mt = 1.0;
   int e = 0;
   for (int k = 0; k < r; ++k) {
     int eu, em;
-    double u = frexp(fabs(LU[k * r + k]), &eu);
+    double u = frexp(fabs(LU[rowmap[k] * r + k]), &eu);
     mt = frexp(mt * u, &em);
     e += eu + em;
   }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/cur.h"
 
@@ -103,6 +104,11 @@ struct cur_ctx_s {
   int32_t* host_flag;   // pinned host word for polling
   int cu_count;
   int last_pinv;        // cur_assemble used the pseudo-inverse
+  // measurement counters (cur_profile_*)
+  int prof_on;
+  unsigned long long* prof_bytes;   // device counter of algorithmic pass bytes
+  std::vector<hipEvent_t>* prof_ev; // event pairs of the current selection
+  cur_profile prof;
 };
 
 namespace cur {

@@ -22,6 +22,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -140,6 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
   }
   const Node& L = prev[nd.child0];
   const Node& R = prev[nd.child1];
+  __shared__ int s_st, nc_sh;
   if (tid == 0) {
     const int qL = L.q, qR = R.q;
     // sorted merge of two ascending lists of original column indices
@@ -200,10 +203,12 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
         nd.st = ST_ACA;
       }
     }
+    s_st = nd.st;
+    nc_sh = nd.nc;
   }
   __syncthreads();
-  if (nd.st == ST_ACA)
-    for (int cc = tid; cc < nd.nc; cc += blockDim.x) nd.colmap[cc] = cc;
+  if (s_st == ST_ACA)
+    for (int cc = tid; cc < nc_sh; cc += blockDim.x) nd.colmap[cc] = cc;
 }
 
 // parent panel column c = child panel column (srcpos), for all merge nodes
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_build(Node* nodes, const Nod
 // tile's argmax.  Writes the tile winner and its full row (in the layout the
 // next step reads) to the node's partial arrays.
 template <typename T, int RMAX>
-__global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
+__global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long long* prof) {
   Node& nd = nodes[blockIdx.y];
   const int st = nd.st;
   if (st != ST_ACA && st != ST_ROW_FRESH && st != ST_ROW_SWAP) return;
@@ -258,6 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
     const T* src = (t <= 1) ? P : W;
     if (t == 0) {
       if (valid)
+#pragma unroll 8
         for (int c = 0; c < na; ++c) {
           const T x = src[(int64_t)c * m + row];
           Cand o;
@@ -276,20 +282,27 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
       const double* f = nd.vec;
       if (valid) {
         const T g = src[(int64_t)pc * m + row];
-        for (int c = 0; c < na; ++c) {
-          if (c == pc) continue;
-          T x = src[(int64_t)c * m + row];
-          x = fma_t<T>(-g, (T)f[c], x);
-          if (row == pi) x = (T)0;
-          const int np = (c == na - 1) ? pc : c;
-          W[(int64_t)np * m + row] = x;
-          Cand o;
-          o.val = fabs((double)x);
-          o.sval = (double)x;
-          o.key = row * nc + cmap[c];
-          o.row = row;
-          o.pos = np;
-          cand_take(best, o);
+        constexpr int U = 8;  // independent loads in flight per lane
+        for (int c0 = 0; c0 < na; c0 += U) {
+          T xs[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) xs[u] = (c0 + u < na) ? src[(int64_t)(c0 + u) * m + row] : (T)0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int c = c0 + u;
+            if (c >= na || c == pc) continue;
+            T x = fma_t<T>(-g, (T)f[c], xs[u]);
+            if (row == pi) x = (T)0;
+            const int np = (c == na - 1) ? pc : c;
+            W[(int64_t)np * m + row] = x;
+            Cand o;
+            o.val = fabs((double)x);
+            o.sval = (double)x;
+            o.key = row * nc + cmap[c];
+            o.row = row;
+            o.pos = np;
+            cand_take(best, o);
+          }
         }
       }
       rowsrc = W;
@@ -319,10 +332,17 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
           double acc[CB];
 #pragma unroll
           for (int j = 0; j < CB; ++j) acc[j] = 0.0;
-          for (int k = 0; k < r; ++k) {
-            const double pk = (double)P[(int64_t)sJp[k] * m + row];
+          constexpr int U = 8;
+          for (int k0 = 0; k0 < r; k0 += U) {
+            double pk[U];
 #pragma unroll
-            for (int j = 0; j < CB; ++j) acc[j] = fma(pk, sX[k * CB + j], acc[j]);
+            for (int u = 0; u < U; ++u) pk[u] = (k0 + u < r) ? (double)P[(int64_t)sJp[k0 + u] * m + row] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              if (k0 + u >= r) break;
+#pragma unroll
+              for (int j = 0; j < CB; ++j) acc[j] = fma(pk[u], sX[(k0 + u) * CB + j], acc[j]);
+            }
           }
 #pragma unroll
           for (int j = 0; j < CB; ++j) {
@@ -349,19 +369,27 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
       const double* v = nd.vec;
       if (valid) {
         const T g = W[(int64_t)ks * m + row];
-        for (int c = 0; c < r; ++c) {
-          T b = W[(int64_t)c * m + row];
-          b = fma_t<T>(-g, (T)v[c], b);
-          if (row == is) b = (c == ks) ? (T)1 : (T)0;
-          W[(int64_t)c * m + row] = b;
-          if (slot < 0) {
-            Cand o;
-            o.val = fabs((double)b);
-            o.sval = (double)b;
-            o.key = row * r + c;
-            o.row = row;
-            o.pos = c;
-            cand_take(best, o);
+        constexpr int U = 8;
+        for (int c0 = 0; c0 < r; c0 += U) {
+          T bs[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) bs[u] = (c0 + u < r) ? W[(int64_t)(c0 + u) * m + row] : (T)0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int c = c0 + u;
+            if (c >= r) continue;
+            T b = fma_t<T>(-g, (T)v[c], bs[u]);
+            if (row == is) b = (c == ks) ? (T)1 : (T)0;
+            W[(int64_t)c * m + row] = b;
+            if (slot < 0) {
+              Cand o;
+              o.val = fabs((double)b);
+              o.sval = (double)b;
+              o.key = row * r + c;
+              o.row = row;
+              o.pos = c;
+              cand_take(best, o);
+            }
           }
         }
       }
@@ -371,6 +399,14 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
   }
 
   best = block_argmax(best, sc);
+  if (prof && tid == 0) {
+    // algorithmic bytes of this tile: working columns read + columns written
+    const int64_t rows = min((int64_t)kTileRows, m - row0);
+    int64_t cols;
+    if (st == ST_ACA) cols = (nd.t == 0) ? nd.na : 2 * nd.na - 1;
+    else cols = 2 * (int64_t)r;
+    atomicAdd(prof, (unsigned long long)(rows * cols * (int64_t)sizeof(T)));
+  }
   if (tid == 0) {
     Partial p;
     p.val = best.val;
@@ -381,10 +417,13 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes) {
     p.pad = 0;
     nd.part[tile] = p;
   }
-  if (best.row >= 0) {
+  // The winner's row was just written by the wavefront that owns it; that
+  // same wavefront copies it out (a wavefront's own stores are visible to its
+  // later loads; stores of other wavefronts are not ordered by the barrier).
+  if (best.row >= 0 && (int)((best.row - row0) >> 6) == (tid >> 6)) {
     const int ld = max(nd.ncmax, r);
     double* pr = nd.prow + (int64_t)tile * ld;
-    for (int c = tid; c < rowlen; c += kThreads) pr[c] = (double)rowsrc[(int64_t)c * m + best.row];
+    for (int c = tid & 63; c < rowlen; c += 64) pr[c] = (double)rowsrc[(int64_t)c * m + best.row];
   }
 }
 
@@ -416,13 +455,21 @@ struct CtlShared {
 
 template <typename T, int RMAX>
 struct CtlLds {
-  static constexpr int CH = RMAX <= 64 ? RMAX : 16;  // inverse column chunk
+  static constexpr int CH = RMAX <= 64 ? RMAX : 16;     // inverse column chunk
+  static constexpr int BCCAP = RMAX <= 64 ? 8192 : 1;  // doubles of Bc kept in LDS
+  static constexpr int INSCAP = 4096;                  // candidate flags kept in LDS
   double A[RMAX * RMAX];   // G / LU, later X
   double B[RMAX * CH];     // inverse chunk, later columns of A(I, Jc)
-  double lk[RMAX];
+  double Bcl[BCCAP];       // column interpolation matrix when it fits
+  int64_t sI[RMAX];        // working copies of I and Jp
+  int32_t sJp[RMAX];
   int perm[RMAX];
   int64_t tmp64[RMAX];
   int tmp32[RMAX];
+  static constexpr int ROWKCAP = 256;
+  uint8_t insel[INSCAP];
+  double wv[RMAX];
+  double rowk[ROWKCAP];
   Cand sc[kThreads / 64];
   CtlShared s;
 };
@@ -458,26 +505,32 @@ __device__ bool ctl_build(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_v
   const T* P = (const T*)nd.panel;
   for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
     const int a = idx / r, b = idx % r;
-    L.A[idx] = (double)P[(int64_t)nd.Jp[b] * m + nd.I[a]];
+    L.A[idx] = (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
   }
   __syncthreads();
-  if (!block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv)) return false;
-  if (want_vol && threadIdx.x == 0) lu_volume(L.A, r, &L.s.vol_m, &L.s.vol_e);
-  if (want_X) block_lu_inverse(L.A, L.perm, r, L.B, CtlLds<T, RMAX>::CH, nd.X);
+  if (!block_gepp(L.A, r, L.perm, &L.s.spiv)) return false;
+  if (want_vol && threadIdx.x == 0) lu_volume(L.A, L.perm, r, &L.s.vol_m, &L.s.vol_e);
+  if (want_X) {
+    if constexpr (RMAX <= 64)
+      block_lu_inverse_reg<RMAX>(L.A, L.perm, r, L.B, nd.X, L.A);
+    else
+      block_lu_inverse(L.A, L.perm, r, L.B, CtlLds<T, RMAX>::CH, nd.X);
+  }
   __syncthreads();
   return true;
 }
 
 template <typename T, int RMAX>
 __device__ void ctl_sort_IJ(Node& nd, CtlLds<T, RMAX>& L, int n) {
-  block_sort<int64_t>(nd.I, n, L.tmp64);
-  block_sort<int32_t>(nd.Jp, n, L.tmp32);
+  (void)nd;
+  block_sort<int64_t>(L.sI, n, L.tmp64);
+  block_sort<int32_t>(L.sJp, n, L.tmp32);
 }
 
 // Fresh column interpolation matrix Bc = X A(I, Jc) (r x nc, row-major, ld ncmax),
 // sums over k ascending, then column Jp[k] := e_k.  X is in L.A.
 template <typename T, int RMAX>
-__device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L) {
+__device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
   const int r = nd.r, nc = L.s.nc, ld = nd.ncmax;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
@@ -486,30 +539,39 @@ __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L) {
     const int nb = min(CH, nc - c0);
     for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
       const int k = idx / nb, j = idx % nb;
-      L.B[k * CH + j] = (double)P[(int64_t)(c0 + j) * m + nd.I[k]];
+      L.B[k * CH + j] = (double)P[(int64_t)(c0 + j) * m + L.sI[k]];
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
       const int a = idx / nb, j = idx % nb;
       double s = 0.0;
       for (int k = 0; k < r; ++k) s = fma(L.A[a * r + k], L.B[k * CH + j], s);
-      nd.Bc[(int64_t)a * ld + c0 + j] = s;
+      bc[(int64_t)a * ld + c0 + j] = s;
     }
     __syncthreads();
   }
   for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
     const int k = idx / r, a = idx % r;
-    nd.Bc[(int64_t)a * ld + nd.Jp[k]] = (a == k) ? 1.0 : 0.0;
+    bc[(int64_t)a * ld + L.sJp[k]] = (a == k) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  if (bc == L.Bcl) __syncthreads();
+  else block_global_sync();
 }
 
-// Load X (written by block_lu_inverse to nd.X) into L.A.
+// X into L.A: the register inverse (r <= 64) already left it there; the LDS
+// inverse wrote it to nd.X only, from which it is read back after the block
+// has published its global stores.
 template <typename T, int RMAX>
 __device__ void ctl_load_X(Node& nd, CtlLds<T, RMAX>& L) {
-  const int r = nd.r;
-  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
-  __syncthreads();
+  if constexpr (RMAX > 64) {
+    const int r = nd.r;
+    block_global_sync();
+    for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
+    __syncthreads();
+  } else {
+    (void)nd;
+    (void)L;
+  }
 }
 
 // The whole COL phase of one node (maxvol on A(I, Jc)^T with I fixed).
@@ -517,6 +579,9 @@ __device__ void ctl_load_X(Node& nd, CtlLds<T, RMAX>& L) {
 template <typename T, int RMAX>
 __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   const int r = nd.r, nc = L.s.nc, ld = nd.ncmax, tid = threadIdx.x;
+  double* bc = ((int64_t)r * ld <= CtlLds<T, RMAX>::BCCAP) ? L.Bcl : nd.Bc;
+  uint8_t* insel = (nc <= CtlLds<T, RMAX>::INSCAP) ? L.insel : nd.insel;
+  const int guard_max = 4 * nd.smax + 16;
   ctl_sort_IJ(nd, L, r);
   if (tid == 0) {
     L.s.phase_swaps = 0;
@@ -524,22 +589,29 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   }
   __syncthreads();
   if (nc > r) {
-    for (int c = tid; c < nc; c += kThreads) nd.insel[c] = 0;
-    __syncthreads();
-    for (int k = tid; k < r; k += kThreads) nd.insel[nd.Jp[k]] = 1;
+    for (int c = tid; c < nc; c += kThreads) insel[c] = 0;
+    if (insel == L.insel) __syncthreads();
+    else block_global_sync();
+    for (int k = tid; k < r; k += kThreads) insel[L.sJp[k]] = 1;
+    if (insel != L.insel) block_global_sync();
     if (!ctl_build(nd, L, true, false)) {
-      if (tid == 0) L.s.err = CUR_ERR_INTERNAL;
+      if (tid == 0) L.s.err = 101;
     } else {
       ctl_load_X(nd, L);
-      ctl_fresh_bc(nd, L);
+      ctl_fresh_bc(nd, L, bc);
       if (tid == 0) L.s.refreshes++;
       __syncthreads();
-      for (int guard = 0; guard < (1 << 30); ++guard) {
+      for (int guard = 0;; ++guard) {
+        if (guard >= guard_max) {
+          if (tid == 0) L.s.err = 102;
+          __syncthreads();
+          break;
+        }
         Cand b = cand_none();
         for (int idx = tid; idx < r * nc; idx += kThreads) {
           const int c = idx / r, k = idx % r;
-          if (nd.insel[c]) continue;
-          const double x = nd.Bc[(int64_t)k * ld + c];
+          if (insel[c]) continue;
+          const double x = bc[(int64_t)k * ld + c];
           Cand o;
           o.val = fabs(x);
           o.sval = x;
@@ -552,11 +624,11 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
         if (b.row < 0 || b.val <= lim) {
           if (L.s.since == 0) break;
           if (!ctl_build(nd, L, true, false)) {
-            if (tid == 0) L.s.err = CUR_ERR_INTERNAL;
+            if (tid == 0) L.s.err = 103;
             break;
           }
           ctl_load_X(nd, L);
-          ctl_fresh_bc(nd, L);
+          ctl_fresh_bc(nd, L, bc);
           if (tid == 0) {
             L.s.refreshes++;
             L.s.since = 0;
@@ -572,30 +644,33 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
         // swap candidate column c* into slot k*
         const int ks = (int)b.row, cs = b.pos;
         const double p = b.sval;
-        double* wv = nd.vec;              // w (r)
-        double* rowk = nd.vec + RMAX;     // old row k* of Bc (nc)
+        double* wv = L.wv;                // w (r)
+        double* rowk = (nc <= CtlLds<T, RMAX>::ROWKCAP) ? L.rowk : nd.vec + RMAX;  // old row k*
         for (int a = tid; a < r; a += kThreads) {
-          const double x = nd.Bc[(int64_t)a * ld + cs];
+          const double x = bc[(int64_t)a * ld + cs];
           wv[a] = (a == ks) ? (p - 1.0) / p : x / p;
         }
-        for (int c = tid; c < nc; c += kThreads) rowk[c] = nd.Bc[(int64_t)ks * ld + c];
-        __syncthreads();
+        for (int c = tid; c < nc; c += kThreads) rowk[c] = bc[(int64_t)ks * ld + c];
+        if (rowk == L.rowk) __syncthreads();
+        else block_global_sync();
         for (int idx = tid; idx < r * nc; idx += kThreads) {
           const int a = idx / nc, c = idx % nc;
-          double x = fma(-wv[a], rowk[c], nd.Bc[(int64_t)a * ld + c]);
+          double x = fma(-wv[a], rowk[c], bc[(int64_t)a * ld + c]);
           if (c == cs) x = (a == ks) ? 1.0 : 0.0;
-          nd.Bc[(int64_t)a * ld + c] = x;
+          bc[(int64_t)a * ld + c] = x;
         }
-        __syncthreads();
+        if (bc == L.Bcl) __syncthreads();
+        else block_global_sync();
         if (tid == 0) {
-          nd.insel[nd.Jp[ks]] = 0;
-          nd.insel[cs] = 1;
-          nd.Jp[ks] = cs;
+          insel[L.sJp[ks]] = 0;
+          insel[cs] = 1;
+          L.sJp[ks] = cs;
           L.s.swaps++;
           L.s.phase_swaps++;
           L.s.since++;
         }
-        __syncthreads();
+        if (insel == L.insel) __syncthreads();
+        else block_global_sync();
       }
     }
   }
@@ -632,6 +707,10 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     s.vol_m = nd.vol_m; s.vol_e = nd.vol_e;
     s.mode = M_EXIT;
   }
+  for (int k = tid; k < r; k += kThreads) {
+    L.sI[k] = nd.I[k];
+    L.sJp[k] = nd.Jp[k];
+  }
   __syncthreads();
   const int st0 = L.s.st;
 
@@ -652,8 +731,8 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
         s.q = s.t;
         s.mode = M_FINISH_SHORT;
       } else {
-        nd.I[s.t] = w.row;
-        nd.Jp[s.t] = nd.colmap[w.pos];
+        L.sI[s.t] = w.row;
+        L.sJp[s.t] = nd.colmap[w.pos];
         s.t++;
         s.q = s.t;
         if (s.t == s.steps) {
@@ -695,7 +774,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
         s.pend_i = w.row;
         s.pend_k = w.pos;
         s.pend_p = w.sval;
-        nd.I[w.pos] = w.row;
+        L.sI[w.pos] = w.row;
         s.swaps++;
         s.phase_swaps++;
         s.since++;
@@ -718,7 +797,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
       // tentative stop after swaps: recompute B fresh for the current orders
       if (!ctl_build(nd, L, true, false)) {
         if (tid == 0) {
-          L.s.err = CUR_ERR_INTERNAL;
+          L.s.err = 104;
           L.s.mode = M_ROW_END;
         }
       } else if (tid == 0) {
@@ -752,7 +831,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
         if (tid == 0) L.s.mode = M_ROW_END;
       } else if (!ctl_build(nd, L, true, false)) {
         if (tid == 0) {
-          L.s.err = CUR_ERR_INTERNAL;
+          L.s.err = 105;
           L.s.mode = M_ROW_END;
         }
       } else if (tid == 0) {
@@ -778,7 +857,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     } else if (mode == M_FINISH) {
       ctl_sort_IJ(nd, L, r);
       if (!L.s.err) {
-        if (!ctl_build(nd, L, false, true) && tid == 0) L.s.err = CUR_ERR_INTERNAL;
+        if (!ctl_build(nd, L, false, true) && tid == 0) L.s.err = 106;
       }
       __syncthreads();
       if (tid == 0) {
@@ -798,7 +877,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
       __syncthreads();
     } else {
       if (tid == 0) {
-        L.s.err = CUR_ERR_INTERNAL;
+        L.s.err = 107;
         L.s.st = ST_DONE;
         L.s.mode = M_EXIT;
         atomicAdd(done, 1);
@@ -807,6 +886,10 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     }
   }
   __syncthreads();
+  for (int k = tid; k < r; k += kThreads) {
+    nd.I[k] = L.sI[k];
+    nd.Jp[k] = L.sJp[k];
+  }
   if (tid == 0) {
     const CtlShared& s = L.s;
     nd.st = s.st; nd.t = s.t; nd.q = s.q; nd.na = s.na; nd.steps = s.steps;
@@ -854,8 +937,8 @@ struct SelectPlan {
 static int rmax_bucket(int r) { return r <= 32 ? 32 : (r <= 64 ? 64 : 128); }
 
 template <typename T, int RMAX>
-static void launch_pass(Node* nodes, int count, int tiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass<T, RMAX>), dim3(tiles, count), dim3(kThreads), 0, s, nodes);
+static void launch_pass(Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass<T, RMAX>), dim3(tiles, count), dim3(kThreads), 0, s, nodes, prof);
 }
 template <typename T, int RMAX>
 static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
@@ -863,10 +946,21 @@ static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, hipSt
 }
 
 template <typename T>
-static void pass_any(int rb, Node* nodes, int count, int tiles, hipStream_t s) {
-  if (rb == 32) launch_pass<T, 32>(nodes, count, tiles, s);
-  else if (rb == 64) launch_pass<T, 64>(nodes, count, tiles, s);
-  else launch_pass<T, 128>(nodes, count, tiles, s);
+static void pass_any(int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s) {
+  if (rb == 32) launch_pass<T, 32>(nodes, count, tiles, prof, s);
+  else if (rb == 64) launch_pass<T, 64>(nodes, count, tiles, prof, s);
+  else launch_pass<T, 128>(nodes, count, tiles, prof, s);
+}
+
+// Event pair around a pass launch when the measurement counters are on.
+static hipEvent_t prof_event(cur_ctx ctx, size_t idx) {
+  std::vector<hipEvent_t>& ev = *ctx->prof_ev;
+  while (ev.size() <= idx) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev.push_back(e);
+  }
+  return ev[idx];
 }
 template <typename T>
 static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
@@ -878,7 +972,7 @@ static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, 
 // Runs pass/ctl iterations on one level until all `count` nodes are done.
 template <typename T>
 static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int tiles, int32_t* d_done,
-                            int64_t max_iters) {
+                            int64_t max_iters, size_t& prof_used) {
   hipStream_t s = ctx->stream;
   volatile int32_t* h = ctx->host_flag;
   hipEvent_t ev;
@@ -890,7 +984,19 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
   cur_status rc = CUR_OK;
   for (;;) {
     for (int j = 0; j < K; ++j) {
-      pass_any<T>(rb, nodes, count, tiles, s);
+      if (ctx->prof_on) {
+        hipEvent_t e0 = prof_event(ctx, prof_used), e1 = prof_event(ctx, prof_used + 1);
+        if (e0 && e1) {
+          (void)hipEventRecord(e0, s);
+          pass_any<T>(rb, nodes, count, tiles, ctx->prof_bytes, s);
+          (void)hipEventRecord(e1, s);
+          prof_used += 2;
+        } else {
+          pass_any<T>(rb, nodes, count, tiles, ctx->prof_bytes, s);
+        }
+      } else {
+        pass_any<T>(rb, nodes, count, tiles, nullptr, s);
+      }
       ctl_any<T>(rb, nodes, count, d_done, 0, s);
     }
     it += K;
@@ -1095,7 +1201,8 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
   hipLaunchKernelGGL((k_panel_from_A<T>), dim3((m + kTR - 1) / kTR, (leafmax + 63) / 64, b),
                      dim3(kThreads), 0, s, L0, A, lda, d_col0);
   const int64_t iter_bound = 16 * (int64_t)(r + 4) + 8 * (int64_t)smax + 4096;
-  cur_status rc = run_level<T>(ctx, rb, L0, b, ntiles, d_done + 0, iter_bound);
+  size_t prof_used = 0;
+  cur_status rc = run_level<T>(ctx, rb, L0, b, ntiles, d_done + 0, iter_bound, prof_used);
   if (rc != CUR_OK) return rc;
 
   // ---- merges
@@ -1107,7 +1214,7 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
     hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev, dd);
     const int gx = (int)std::min<int64_t>((m + kThreads - 1) / kThreads, 64);
     hipLaunchKernelGGL((k_panel_build<T>), dim3(gx, 2 * r, cnt), dim3(kThreads), 0, s, cur, prev);
-    rc = run_level<T>(ctx, rb, cur, cnt, ntiles, dd, iter_bound);
+    rc = run_level<T>(ctx, rb, cur, cnt, ntiles, dd, iter_bound, prof_used);
     if (rc != CUR_OK) return rc;
   }
 
@@ -1125,7 +1232,27 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
     CUR_HIP_CHECK(hipMemcpyAsync(eJ.data(), d_expJ, sizeof(int64_t) * eJ.size(), hipMemcpyDeviceToHost, s));
   }
   CUR_HIP_CHECK(hipStreamSynchronize(s));
+  if (ctx->prof_on) {
+    std::vector<hipEvent_t>& ev = *ctx->prof_ev;
+    for (size_t k = 0; k + 1 < prof_used; k += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) {
+        ctx->prof.seconds += 1e-3 * ms;
+        ctx->prof.launches += 1;
+      }
+    }
+  }
 
+  if (std::getenv("CUR_DEBUG")) {
+    for (size_t l = 0; l < levels.size(); ++l)
+      for (int k = 0; k < levels[l].count; ++k) {
+        const Node& nd = h[levels[l].first + k];
+        if (nd.err || nd.st != ST_DONE)
+          std::fprintf(stderr, "cur: node level %zu index %d kind %d st %d err %d phase %d swaps %d "
+                       "phases %d refreshes %d q %d nc %d\n", l, k, nd.kind, nd.st, nd.err, nd.phase,
+                       nd.swaps, nd.phases, nd.refreshes, nd.q, nd.nc);
+      }
+  }
   cur_status result = CUR_OK;
   int32_t nodes = 0, phases = 0, refreshes = 0;
   int64_t swaps = 0;

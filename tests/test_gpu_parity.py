@@ -93,6 +93,22 @@ def test_select_f64_c2_recipe_small(orc, n):
     assert_same_selection(g, o)
 
 
+def test_select_is_deterministic_across_calls(orc):
+    # repeated selections of one matrix (arena reused, assembly interleaved)
+    # must return identical indices and counters, equal to the oracle's
+    A = W.c2(7, device=DEV, n=2048)
+    say("case determinism c2-recipe n=2048 x6")
+    o = orc.select(A.cpu().numpy(), 64)
+    for k in range(6):
+        g = cur.select(A, 64)
+        np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+        np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+        assert (g["swaps"], g["phases"], g["refreshes"]) == (o["swaps"], o["phases"], o["refreshes"])
+        if k % 2:
+            C, U, R = cur.assemble(A, g["I"], g["J"])
+            cur.residual(A, C, U, R)
+
+
 def test_select_f64_rank_short(orc):
     rng = np.random.default_rng(9)
     A = torch.from_numpy(rng.standard_normal((300, 3)) @ rng.standard_normal((3, 400))).to(DEV)
