@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
     L.A[idx] = (double)A[I[a] * lda + J[b]];
   }
   __syncthreads();
-  const bool ok = block_gepp(L.A, r, L.perm, &L.spiv);
+  const bool ok = block_gepp(L.A, r, L.perm, L.lk, &L.spiv);
   if (tid == 0) {
     int use_pinv = 1;
     if (ok) {

@@ -89,17 +89,16 @@ __device__ __forceinline__ void block_global_sync() {
 // position p).  The arithmetic is exactly that of swapping rows: pivot of
 // column k = largest |G(p,k)| over positions p >= k, ties to the smallest p;
 // multiplier l = G(p,k) / G(k,k) stored in place; G(p,c) = fma(-l, G(k,c), G(p,c)).
-// Each row is updated by a group of lanes of one wavefront, which makes the
-// in-place store of l race-free.  spiv: one int of LDS.  Returns false
-// (uniformly) if G is singular.
-__device__ bool block_gepp(double* G, int r, int* rowmap, int* spiv) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int i = tid; i < r; i += blockDim.x) rowmap[i] = i;
+// Every LDS location is written in a phase in which no other thread reads it
+// (phases separated by block barriers).  lk: r doubles of LDS; spiv: one int.
+// Returns false (uniformly) if G is singular.
+__device__ bool block_gepp(double* G, int r, int* rowmap, double* lk, int* spiv) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
+  for (int i = tid; i < r; i += nt) rowmap[i] = i;
   __syncthreads();
-  constexpr int LPR = 16;             // lanes per row
-  const int rpw = 64 / LPR;           // rows per wavefront per round
-  const int grp = lane / LPR, sub = lane % LPR;
   for (int k = 0; k < r; ++k) {
+    // phase A: pivot search (wavefront 0); the winner is published after the
+    // cross-lane reduction, which every lane's load feeds.
     if (wave == 0) {
       double best = -1.0;
       int arg = r;
@@ -128,14 +127,18 @@ __device__ bool block_gepp(double* G, int r, int* rowmap, int* spiv) {
     if (*spiv < 0) return false;
     const int pr = rowmap[k];
     const double d = G[pr * r + k];
-    for (int p0 = k + 1 + wave * rpw; p0 < r; p0 += nw * rpw) {
-      const int p = p0 + grp;
-      if (p < r) {
-        const int ph = rowmap[p];
-        const double l = G[ph * r + k] / d;
-        for (int c = k + 1 + sub; c < r; c += LPR) G[ph * r + c] = fma(-l, G[pr * r + c], G[ph * r + c]);
-        if (sub == 0) G[ph * r + k] = l;
-      }
+    // phase B: multipliers of the rows below the pivot position
+    for (int p = k + 1 + tid; p < r; p += nt) lk[p] = G[rowmap[p] * r + k] / d;
+    __syncthreads();
+    // phase C: trailing update; column k receives the multipliers
+    const int cols = r - k, rows = r - k - 1;
+    for (int idx = tid; idx < rows * cols; idx += nt) {
+      const int p = k + 1 + idx / cols, c = k + idx % cols;
+      const int ph = rowmap[p];
+      if (c == k)
+        G[ph * r + k] = lk[p];
+      else
+        G[ph * r + c] = fma(-lk[p], G[pr * r + c], G[ph * r + c]);
     }
     __syncthreads();
   }

@@ -14,6 +14,7 @@ namespace cur {
 constexpr int kThreads = 256;      // threads per workgroup of every kernel here
 constexpr int kTileRows = 256;     // rows of a row-pass tile (one row per thread)
 constexpr int kMetaFields = 10;    // fields of a cur_trace meta record
+constexpr int kDbgRing = 64;       // swap decisions remembered per node
 
 // Per-node state machine.  A node is a leaf (one column block), a merge of two
 // children, or a promoted copy of an odd last child.
@@ -34,7 +35,7 @@ struct Partial {
   int64_t key;  // scan-order key: smaller wins ties
   int64_t row;  // row index
   int32_t pos;  // column position in the working layout
-  int32_t pad;
+  int32_t seq;  // the node's pass sequence number when written
 };
 
 struct Node {
@@ -46,7 +47,7 @@ struct Node {
   int32_t smax;      // swap budget
   int32_t kind;      // NodeKind
   int32_t child0, child1;  // indices into the previous level's node table (-1: none)
-  int32_t pad0;
+  int32_t seq;       // pass sequence number: stamps the tile winners of a pass
   double tau;        // swap iff |B| > 1 + tau
   double theta;      // numerical-zero pivot threshold of ACA
   void* panel;       // m x ncmax, column-major (ld m), element T: A(:, Jc)
@@ -55,13 +56,13 @@ struct Node {
   double* Bc;        // r x ncmax row-major: column interpolation matrix
   double* vec;       // max(ncmax, r): pivot-row factors f (ACA) or v (row swap)
   Partial* part;     // ntiles
-  double* prow;      // ntiles x max(ncmax, r): winner row of each tile
   int64_t* Jc;       // ncmax: original column index of each candidate (ascending)
   int32_t* colmap;   // ncmax: ACA layout position -> candidate position
   int32_t* srcpos;   // ncmax: merge: (child << 24) | position in the child's panel
   uint8_t* insel;    // ncmax: candidate currently in J
   int64_t* I;        // r: selected rows (current order)
   int32_t* Jp;       // r: selected candidate positions (current order)
+  double* dbg;       // 4 x kDbgRing swap log (kind, index, slot, pivot) for diagnostics
   // ---- dynamic state (device) ----
   int32_t nc;        // number of candidates
   int32_t st;        // NodeState

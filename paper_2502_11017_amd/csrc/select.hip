@@ -254,8 +254,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
   __shared__ Cand sc[kThreads / 64];
 
   Cand best = cand_none();
-  const T* rowsrc = W;
-  int rowlen = r;
 
   if (st == ST_ACA) {
     const int t = nd.t, na = nd.na, nc = nd.nc;
@@ -274,8 +272,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
           o.pos = c;
           cand_take(best, o);
         }
-      rowsrc = P;
-      rowlen = na;
     } else {
       const int pc = nd.pend_k;
       const int64_t pi = nd.pend_i;
@@ -305,8 +301,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
           }
         }
       }
-      rowsrc = W;
-      rowlen = na - 1;
     }
   } else {
     // masked rows: the selected ones, with their slot k
@@ -394,8 +388,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
         }
       }
     }
-    rowsrc = W;
-    rowlen = r;
   }
 
   best = block_argmax(best, sc);
@@ -414,16 +406,8 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
     p.key = best.key;
     p.row = best.row;
     p.pos = best.pos;
-    p.pad = 0;
+    p.seq = nd.seq;
     nd.part[tile] = p;
-  }
-  // The winner's row was just written by the wavefront that owns it; that
-  // same wavefront copies it out (a wavefront's own stores are visible to its
-  // later loads; stores of other wavefronts are not ordered by the barrier).
-  if (best.row >= 0 && (int)((best.row - row0) >> 6) == (tid >> 6)) {
-    const int ld = max(nd.ncmax, r);
-    double* pr = nd.prow + (int64_t)tile * ld;
-    for (int c = tid & 63; c < rowlen; c += 64) pr[c] = (double)rowsrc[(int64_t)c * m + best.row];
   }
 }
 
@@ -441,6 +425,7 @@ enum CtlMode : int32_t {
 
 struct CtlShared {
   int mode;
+  int stale;
   int st, t, q, na, steps, nc;
   int is_short, nocap, err, phase, phase_swaps, since, swaps, phases, refreshes;
   int pend_k;
@@ -461,6 +446,7 @@ struct CtlLds {
   double A[RMAX * RMAX];   // G / LU, later X
   double B[RMAX * CH];     // inverse chunk, later columns of A(I, Jc)
   double Bcl[BCCAP];       // column interpolation matrix when it fits
+  double lk[RMAX];         // LU multipliers of one elimination step
   int64_t sI[RMAX];        // working copies of I and Jp
   int32_t sJp[RMAX];
   int perm[RMAX];
@@ -468,18 +454,31 @@ struct CtlLds {
   int tmp32[RMAX];
   static constexpr int ROWKCAP = 256;
   uint8_t insel[INSCAP];
+  int slot[kThreads];      // column phase: slot k of a selected candidate, -1 otherwise
   double wv[RMAX];
   double rowk[ROWKCAP];
   Cand sc[kThreads / 64];
   CtlShared s;
 };
 
+// Append one swap decision to the node's diagnostic ring (thread 0 only).
+__device__ __forceinline__ void dbg_log(Node& nd, int count, double kind, double idx, double slot, double piv) {
+  double* d = nd.dbg + 4 * (count % kDbgRing);
+  d[0] = kind;
+  d[1] = idx;
+  d[2] = slot;
+  d[3] = piv;
+}
+
 // Reduce the tile winners of the last pass (the global argmax of the node).
 template <typename T, int RMAX>
 __device__ void ctl_reduce(Node& nd, CtlLds<T, RMAX>& L) {
   Cand b = cand_none();
+  const int seq = nd.seq;
+  int stale = 0;
   for (int tl = threadIdx.x; tl < nd.ntiles; tl += kThreads) {
     const Partial p = nd.part[tl];
+    stale |= (p.seq != seq);  // a tile winner this pass did not write
     Cand o;
     o.val = p.val;
     o.sval = p.sval;
@@ -489,9 +488,12 @@ __device__ void ctl_reduce(Node& nd, CtlLds<T, RMAX>& L) {
     cand_take(b, o);
   }
   b = block_argmax(b, L.sc);
+  stale = __syncthreads_or(stale);
   if (threadIdx.x == 0) {
+    L.s.stale = stale;
     L.s.win = b;
     L.s.wtile = b.row >= 0 ? (int)(b.row / kTileRows) : -1;
+    if (L.s.stale) L.s.err = 120;
   }
   __syncthreads();
 }
@@ -508,7 +510,7 @@ __device__ bool ctl_build(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_v
     L.A[idx] = (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
   }
   __syncthreads();
-  if (!block_gepp(L.A, r, L.perm, &L.s.spiv)) return false;
+  if (!block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv)) return false;
   if (want_vol && threadIdx.x == 0) lu_volume(L.A, L.perm, r, &L.s.vol_m, &L.s.vol_e);
   if (want_X) {
     if constexpr (RMAX <= 64)
@@ -687,6 +689,167 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   __syncthreads();
 }
 
+// The COL phase with one thread per candidate column: thread c (< nc <=
+// kThreads) owns column c of Bc, stored in LDS with leading dimension nc
+// (r * nc <= BCCAP).  Same decisions and per-element arithmetic as
+// ctl_col_phase: fresh Bc(a,c) = sum_k X(a,k) A(I[k],Jc[c]) with k ascending;
+// swap c* into slot k*: Bc(a,c) = fma(-w_a, Bc(k*,c), Bc(a,c)), column c* := e_k*.
+template <typename T, int RMAX>
+__device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
+  const int r = nd.r, nc = L.s.nc, tid = threadIdx.x;
+  const int64_t m = nd.m;
+  const T* P = (const T*)nd.panel;
+  const int guard_max = 4 * nd.smax + 16;
+  uint8_t* insel = L.insel;
+  double* bc = L.Bcl;  // r x nc, element (a, c) at a * nc + c
+  int* slot = L.slot;
+  ctl_sort_IJ(nd, L, r);
+  if (tid == 0) {
+    L.s.phase_swaps = 0;
+    L.s.since = 0;
+  }
+  for (int c = tid; c < nc; c += kThreads) {
+    insel[c] = 0;
+    slot[c] = -1;
+  }
+  __syncthreads();
+  for (int k = tid; k < r; k += kThreads) {
+    insel[L.sJp[k]] = 1;
+    slot[L.sJp[k]] = k;
+  }
+  __syncthreads();
+  const int c = tid;
+  const bool own = c < nc;
+  constexpr int AC = 16;  // rows of a column accumulated per sweep over k
+  constexpr int SW = CtlLds<T, RMAX>::CH;  // columns staged per chunk (L.B is RMAX x SW)
+  static_assert(RMAX <= 64 && SW == RMAX, "column staging assumes L.B of RMAX x RMAX");
+  // fresh Bc: A(I, Jc) is gathered SW columns at a time into L.B (each
+  // owner thread issues its r loads back to back), then each owner forms its
+  // column from X (in L.A) with k ascending per element.
+#define CUR_COL_FRESH()                                                        \
+  for (int c0 = 0; c0 < nc; c0 += SW) {                                        \
+    const bool mine = own && c >= c0 && c < c0 + SW;                           \
+    if (mine) {                                                                \
+      const T* col = P + (int64_t)c * m;                                       \
+      _Pragma("unroll 8") for (int k = 0; k < r; ++k)                          \
+        L.B[k * SW + (c - c0)] = (double)col[L.sI[k]];                         \
+    }                                                                          \
+    __syncthreads();                                                           \
+    if (mine) {                                                                \
+      for (int a0 = 0; a0 < r; a0 += AC) {                                     \
+        double acc[AC];                                                        \
+        _Pragma("unroll") for (int j = 0; j < AC; ++j) acc[j] = 0.0;           \
+        for (int k = 0; k < r; ++k) {                                          \
+          const double pk = L.B[k * SW + (c - c0)];                            \
+          _Pragma("unroll") for (int j = 0; j < AC; ++j)                       \
+            if (a0 + j < r) acc[j] = fma(L.A[(a0 + j) * r + k], pk, acc[j]);   \
+        }                                                                      \
+        _Pragma("unroll") for (int j = 0; j < AC; ++j)                         \
+          if (a0 + j < r) bc[(a0 + j) * nc + c] = acc[j];                      \
+      }                                                                        \
+      const int sl = slot[c];                                                  \
+      if (sl >= 0)                                                             \
+        for (int a = 0; a < r; ++a) bc[a * nc + c] = (a == sl) ? 1.0 : 0.0;    \
+    }                                                                          \
+    __syncthreads();                                                           \
+  }
+  if (!ctl_build(nd, L, true, false)) {
+    if (tid == 0) {
+      int code = 108;  // numerically singular cross
+      for (int a = 0; a < r; ++a) {
+        if (L.sI[a] < 0 || L.sI[a] >= m) code = 132;
+        if (L.sJp[a] < 0 || L.sJp[a] >= nc) code = 133;
+        for (int b = a + 1; b < r; ++b) {
+          if (L.sI[a] == L.sI[b]) code = 130;
+          if (L.sJp[a] == L.sJp[b]) code = 131;
+        }
+      }
+      L.s.err = code;
+    }
+    __syncthreads();
+  } else {
+    CUR_COL_FRESH();
+    if (tid == 0) L.s.refreshes++;
+    __syncthreads();
+    for (int guard = 0;; ++guard) {
+      if (guard >= guard_max) {
+        if (tid == 0) L.s.err = 109;
+        __syncthreads();
+        break;
+      }
+      Cand b = cand_none();
+      if (own && !insel[c]) {
+        for (int a = 0; a < r; ++a) {
+          const double x = bc[a * nc + c];
+          Cand o;
+          o.val = fabs(x);
+          o.sval = x;
+          o.key = (int64_t)c * r + a;
+          o.row = a;
+          o.pos = c;
+          cand_take(b, o);
+        }
+      }
+      b = block_argmax(b, L.sc);
+      if (b.row < 0 || b.val <= lim) {
+        if (L.s.since == 0) break;
+        if (!ctl_build(nd, L, true, false)) {
+          if (tid == 0) L.s.err = 110;
+          __syncthreads();
+          break;
+        }
+        CUR_COL_FRESH();
+        if (tid == 0) {
+          L.s.refreshes++;
+          L.s.since = 0;
+        }
+        __syncthreads();
+        continue;
+      }
+      if (L.s.swaps >= nd.smax) {
+        if (tid == 0) L.s.nocap = 1;
+        __syncthreads();
+        break;
+      }
+      const int ks = (int)b.row, cs = b.pos;
+      const double p = b.sval;
+      for (int a = tid; a < r; a += kThreads) L.wv[a] = (a == ks) ? (p - 1.0) / p : bc[a * nc + cs] / p;
+      __syncthreads();
+      if (own) {
+        const double rk = bc[ks * nc + c];
+        for (int a = 0; a < r; ++a) bc[a * nc + c] = fma(-L.wv[a], rk, bc[a * nc + c]);
+        if (c == cs)
+          for (int a = 0; a < r; ++a) bc[a * nc + c] = (a == ks) ? 1.0 : 0.0;
+      }
+      if (tid == 0) {
+        dbg_log(nd, L.s.swaps, 2.0 + 0.001 * L.s.refreshes, (double)cs, (double)ks, p);
+        const int old = L.sJp[ks];
+        insel[old] = 0;
+        slot[old] = -1;
+        insel[cs] = 1;
+        slot[cs] = ks;
+        L.sJp[ks] = cs;
+        L.s.swaps++;
+        L.s.phase_swaps++;
+        L.s.since++;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+#undef CUR_COL_FRESH
+  if (tid == 0) {
+    L.s.phases++;
+    if (L.s.err || L.s.nocap || L.s.phase_swaps == 0) {
+      L.s.mode = M_FINISH;
+    } else {
+      L.s.phase++;
+      L.s.mode = M_ROW_START;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, int startup) {
   Node& nd = nodes[blockIdx.x];
@@ -706,6 +869,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     s.refreshes = nd.refreshes; s.pend_k = nd.pend_k; s.pend_i = nd.pend_i; s.pend_p = nd.pend_p;
     s.vol_m = nd.vol_m; s.vol_e = nd.vol_e;
     s.mode = M_EXIT;
+    s.stale = 0;
   }
   for (int k = tid; k < r; k += kThreads) {
     L.sI[k] = nd.I[k];
@@ -754,11 +918,12 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     }
     __syncthreads();
     if (L.s.mode == M_EXIT) {
-      // f_c = R(i*, c) / p in the working precision
-      const int ld = max(nd.ncmax, r);
-      const double* pr = nd.prow + (int64_t)L.s.wtile * ld;
+      // f_c = R(i*, c) / p in the working precision, read from the residual the
+      // pass just wrote (the panel itself after the first, read-only, pass)
+      const T* R = (L.s.t == 1) ? (const T*)nd.panel : (const T*)nd.work;
+      const int64_t wr = L.s.pend_i;
       const T p = (T)L.s.pend_p;
-      for (int c = tid; c < L.s.na; c += kThreads) nd.vec[c] = (double)((T)pr[c] / p);
+      for (int c = tid; c < L.s.na; c += kThreads) nd.vec[c] = (double)(R[(int64_t)c * m + wr] / p);
     }
   } else if (st0 == ST_ROW_FRESH || st0 == ST_ROW_SWAP) {
     ctl_reduce(nd, L);
@@ -771,6 +936,9 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
         s.nocap = 1;
         s.mode = M_ROW_END;
       } else {
+        for (int k = 0; k < r; ++k)
+          if (L.sI[k] == w.row) s.err = 121;  // a selected row won: inconsistent pass
+        dbg_log(nd, s.swaps, 1.0 + 0.001 * s.refreshes, (double)w.row, (double)w.pos, w.sval);
         s.pend_i = w.row;
         s.pend_k = w.pos;
         s.pend_p = w.sval;
@@ -784,12 +952,12 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     }
     __syncthreads();
     if (L.s.mode == M_SWAPVEC) {
-      const int ld = max(nd.ncmax, r);
-      const double* pr = nd.prow + (int64_t)L.s.wtile * ld;
+      const T* B = (const T*)nd.work;
+      const int64_t wr = L.s.pend_i;
       const T p = (T)L.s.pend_p;
       const int ks = L.s.pend_k;
       for (int c = tid; c < r; c += kThreads)
-        nd.vec[c] = (c == ks) ? (double)((p - (T)1) / p) : (double)((T)pr[c] / p);
+        nd.vec[c] = (c == ks) ? (double)((p - (T)1) / p) : (double)(B[(int64_t)c * m + wr] / p);
       __syncthreads();
       if (tid == 0) L.s.mode = M_EXIT;
       __syncthreads();
@@ -853,7 +1021,14 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
       }
       __syncthreads();
     } else if (mode == M_COL) {
-      ctl_col_phase(nd, L, lim);
+      if constexpr (RMAX <= 64) {
+        if (L.s.nc <= kThreads && L.s.nc > r && r * L.s.nc <= CtlLds<T, RMAX>::BCCAP)
+          ctl_col_phase_cols(nd, L, lim);
+        else
+          ctl_col_phase(nd, L, lim);
+      } else {
+        ctl_col_phase(nd, L, lim);
+      }
     } else if (mode == M_FINISH) {
       ctl_sort_IJ(nd, L, r);
       if (!L.s.err) {
@@ -892,6 +1067,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
   }
   if (tid == 0) {
     const CtlShared& s = L.s;
+    nd.seq = nd.seq + 1;
     nd.st = s.st; nd.t = s.t; nd.q = s.q; nd.na = s.na; nd.steps = s.steps;
     nd.is_short = s.is_short; nd.nocap = s.nocap; nd.err = s.err; nd.phase = s.phase;
     nd.phase_swaps = s.phase_swaps; nd.since = s.since; nd.swaps = s.swaps; nd.phases = s.phases;
@@ -1013,8 +1189,9 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
         rc = CUR_ERR_DEVICE;
         break;
       }
-      if (*h >= count) break;
+      if (*h >= count) break;  // -1 (copy not landed) reads as "not done"
     }
+    *h = -1;
     e = hipMemcpyAsync((void*)h, d_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(ev, s);
     if (e != hipSuccess) {
@@ -1073,8 +1250,9 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
       set_error("A is zero");
       return CUR_ERR_RANK;
     }
-    const double ulp = sizeof(T) == 8 ? 0x1p-52 : 0x1p-23;
-    theta = (double)std::max(m, n) * ulp * amax;
+    // FP64: max(m,n) 2^-52 ||A||_C, the oracle's threshold.  FP32 path: the
+    // rounding accumulated by r elimination steps in FP32, r 2^-23 ||A||_C.
+    theta = sizeof(T) == 8 ? (double)std::max(m, n) * 0x1p-52 * amax : (double)r * 0x1p-23 * amax;
   }
 
   // ---- plan the tree
@@ -1113,11 +1291,11 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
     per += al(sizeof(double) * r * nc);       // Bc
     per += al(sizeof(double) * (wd + 128 + nc));  // vec (w | rowk)
     per += al(sizeof(Partial) * ntiles);
-    per += al(sizeof(double) * ntiles * wd);  // prow
     per += al(sizeof(int64_t) * nc);          // Jc
     per += al(sizeof(int32_t) * nc) * 2;      // colmap, srcpos
     per += al(nc);                            // insel
     per += al(sizeof(int64_t) * r) + al(sizeof(int32_t) * r);
+    per += al(sizeof(double) * 4 * kDbgRing);
     bytes += per * levels[l].count;
   }
   bytes += al(sizeof(int64_t) * b);  // leaf col0
@@ -1147,13 +1325,13 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
       nd.Bc = (double*)ar.take(sizeof(double) * r * nc);
       nd.vec = (double*)ar.take(sizeof(double) * (wd + 128 + nc));
       nd.part = (Partial*)ar.take(sizeof(Partial) * ntiles);
-      nd.prow = (double*)ar.take(sizeof(double) * ntiles * wd);
       nd.Jc = (int64_t*)ar.take(sizeof(int64_t) * nc);
       nd.colmap = (int32_t*)ar.take(sizeof(int32_t) * nc);
       nd.srcpos = (int32_t*)ar.take(sizeof(int32_t) * nc);
       nd.insel = (uint8_t*)ar.take(nc);
       nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
       nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
+      nd.dbg = (double*)ar.take(sizeof(double) * 4 * kDbgRing);
       if (!nd.panel || !nd.work || !nd.insel || !nd.Jp) {
         set_error("workspace layout overflow");
         return CUR_ERR_INTERNAL;
@@ -1247,13 +1425,27 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
     for (size_t l = 0; l < levels.size(); ++l)
       for (int k = 0; k < levels[l].count; ++k) {
         const Node& nd = h[levels[l].first + k];
-        if (nd.err || nd.st != ST_DONE)
+        if (nd.err || nd.st != ST_DONE || nd.nocap) {
           std::fprintf(stderr, "cur: node level %zu index %d kind %d st %d err %d phase %d swaps %d "
-                       "phases %d refreshes %d q %d nc %d\n", l, k, nd.kind, nd.st, nd.err, nd.phase,
-                       nd.swaps, nd.phases, nd.refreshes, nd.q, nd.nc);
+                       "phases %d refreshes %d q %d nc %d nocap %d\n", l, k, nd.kind, nd.st, nd.err, nd.phase,
+                       nd.swaps, nd.phases, nd.refreshes, nd.q, nd.nc, nd.nocap);
+          std::vector<double> ring(4 * kDbgRing);
+          if (hipMemcpy(ring.data(), nd.dbg, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+            const int n0 = nd.swaps > kDbgRing ? nd.swaps - kDbgRing : 0;
+            for (int q = n0; q < nd.swaps; ++q) {
+              const double* e = &ring[4 * (q % kDbgRing)];
+              std::fprintf(stderr, "  swap %d kind %.3f index %.0f slot %.0f pivot %.17g\n", q, e[0], e[1], e[2], e[3]);
+            }
+          }
+        }
       }
   }
   cur_status result = CUR_OK;
+  for (int k = 0; k < total; ++k)
+    if (h[k].st != ST_DONE) {
+      set_error("a tree node was left unfinished");
+      return CUR_ERR_INTERNAL;
+    }
   int32_t nodes = 0, phases = 0, refreshes = 0;
   int64_t swaps = 0;
   bool nocap = false;
