@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
     if (ok) {
       double umin = HUGE_VAL, umax = 0.0;
       for (int k = 0; k < r; ++k) {
-        const double u = fabs(L.A[L.perm[k] * r + k]);
+        const double u = fabs(L.A[k * r + k]);
         umin = fmin(umin, u);
         umax = fmax(umax, u);
       }
@@ -74,10 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
   }
   __syncthreads();
   if (!L.pinv) {
-    if constexpr (RMAX <= 64)
-      block_lu_inverse_reg<RMAX>(L.A, L.perm, r, L.B, U);
-    else
-      block_lu_inverse(L.A, L.perm, r, L.B, AsmLds<RMAX>::CH, U);
+    block_lu_inverse<AsmLds<RMAX>::CH>(L.A, L.perm, r, L.B, U);
     return;
   }
   // ---- one-sided Jacobi: W = G V with orthogonal columns (cyclic pairs, <= 60 sweeps)

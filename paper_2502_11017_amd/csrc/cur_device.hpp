@@ -83,27 +83,30 @@ __device__ __forceinline__ void block_global_sync() {
 }
 
 // ---------------------------------------------------------------- small dense kernels
-// LU with partial pivoting of the r x r row-major G held in LDS, in place and
-// without moving rows: rowmap[p] is the LDS row that holds position p (rows
-// stay where they were loaded, so rowmap[p] is also the original row of
-// position p).  The arithmetic is exactly that of swapping rows: pivot of
-// column k = largest |G(p,k)| over positions p >= k, ties to the smallest p;
-// multiplier l = G(p,k) / G(k,k) stored in place; G(p,c) = fma(-l, G(k,c), G(p,c)).
-// Every LDS location is written in a phase in which no other thread reads it
-// (phases separated by block barriers).  lk: r doubles of LDS; spiv: one int.
-// Returns false (uniformly) if G is singular.
-__device__ bool block_gepp(double* G, int r, int* rowmap, double* lk, int* spiv) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
-  for (int i = tid; i < r; i += nt) rowmap[i] = i;
+// LU with partial pivoting of the r x r row-major G held in LDS, in place,
+// rows physically swapped as in the textbook algorithm: pivot of column k =
+// largest |G(p,k)| over p >= k, ties to the smallest p; multiplier
+// l = G(p,k) / G(k,k) stored in place; G(p,c) = fma(-l, G(k,c), G(p,c)).
+// perm[k] receives the original row now at position k.  Three phases per
+// step, separated by block barriers, so that no LDS location is written while
+// another thread reads it:
+//   A  wavefront 0 finds the pivot;
+//   B  rows k and piv exchange every column except k, and the multipliers are
+//      formed from the unswapped column k (the swapped row p reads row piv);
+//   C  trailing update of rows p > k, column k receives the multipliers and
+//      the pivot.
+// Threads map to (column = lane-group, row = wave + 4*i): no divisions.
+// lk: r doubles of LDS; spiv: one int.  Returns false (uniformly) if singular.
+__device__ bool block_gepp(double* G, int r, int* perm, double* lk, int* spiv) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int i = tid; i < r; i += blockDim.x) perm[i] = i;
   __syncthreads();
   for (int k = 0; k < r; ++k) {
-    // phase A: pivot search (wavefront 0); the winner is published after the
-    // cross-lane reduction, which every lane's load feeds.
     if (wave == 0) {
       double best = -1.0;
       int arg = r;
       for (int p = k + lane; p < r; p += 64) {
-        const double v = fabs(G[rowmap[p] * r + k]);
+        const double v = fabs(G[p * r + k]);
         if (v > best) { best = v; arg = p; }
       }
 #pragma unroll
@@ -112,33 +115,39 @@ __device__ bool block_gepp(double* G, int r, int* rowmap, double* lk, int* spiv)
         const int oa = __shfl_xor(arg, s, 64);
         if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
       }
-      if (lane == 0) {
-        if (best == 0.0) {
-          *spiv = -1;
-        } else {
-          *spiv = arg;
-          const int t = rowmap[k];
-          rowmap[k] = rowmap[arg];
-          rowmap[arg] = t;
-        }
-      }
+      if (lane == 0) *spiv = (best > 0.0) ? arg : -1;  // zero or non-finite column: singular
     }
     __syncthreads();
-    if (*spiv < 0) return false;
-    const int pr = rowmap[k];
-    const double d = G[pr * r + k];
-    // phase B: multipliers of the rows below the pivot position
-    for (int p = k + 1 + tid; p < r; p += nt) lk[p] = G[rowmap[p] * r + k] / d;
+    const int piv = *spiv;
+    if (piv < 0) return false;
+    const double d = G[piv * r + k];  // the pivot (row piv, before the exchange)
+    // phase B
+    if (piv != k)
+      for (int c = tid; c < r; c += blockDim.x)
+        if (c != k) {
+          const double t = G[k * r + c];
+          G[k * r + c] = G[piv * r + c];
+          G[piv * r + c] = t;
+        }
+    for (int p = k + 1 + tid; p < r; p += blockDim.x) {
+      const int src = (p == piv) ? k : p;  // after the exchange row p holds old row src
+      lk[p] = G[src * r + k] / d;
+    }
+    if (tid == 0 && piv != k) {
+      const int t = perm[k];
+      perm[k] = perm[piv];
+      perm[piv] = t;
+    }
     __syncthreads();
-    // phase C: trailing update; column k receives the multipliers
-    const int cols = r - k, rows = r - k - 1;
-    for (int idx = tid; idx < rows * cols; idx += nt) {
-      const int p = k + 1 + idx / cols, c = k + idx % cols;
-      const int ph = rowmap[p];
-      if (c == k)
-        G[ph * r + k] = lk[p];
-      else
-        G[ph * r + c] = fma(-lk[p], G[pr * r + c], G[ph * r + c]);
+    // phase C
+    for (int c = k + lane; c < r; c += 64) {
+      if (c == k) {
+        if (wave == 0) G[k * r + k] = d;
+        for (int p = k + 1 + wave; p < r; p += nw) G[p * r + k] = lk[p];
+      } else {
+        const double gk = G[k * r + c];
+        for (int p = k + 1 + wave; p < r; p += nw) G[p * r + c] = fma(-lk[p], gk, G[p * r + c]);
+      }
     }
     __syncthreads();
   }
@@ -146,99 +155,49 @@ __device__ bool block_gepp(double* G, int r, int* rowmap, double* lk, int* spiv)
 }
 
 // X = G^{-1} (row-major r x r, written to Xg: global or LDS) from the factors
-// of block_gepp, column chunk by column chunk in the LDS buffer Y (r x ch):
-// forward substitution L y = P e_j with the sum over k ascending, then back
+// of block_gepp, CH columns at a time in the LDS buffer Y (r x CH): forward
+// substitution L y = P e_j with the sum over k ascending, then back
 // substitution U x = y with the sum over k descending and x_k = s / U(k,k).
-// Each element receives its updates in exactly that order.
-__device__ void block_lu_inverse(const double* LU, const int* rowmap, int r, double* Y, int ch,
-                                 double* Xg) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int j0 = 0; j0 < r; j0 += ch) {
-    const int nch = min(ch, r - j0);
-    for (int idx = tid; idx < r * nch; idx += nt) {
-      const int i = idx / nch, jj = idx % nch;
-      Y[i * ch + jj] = (rowmap[i] == j0 + jj) ? 1.0 : 0.0;
-    }
+// Each element receives its updates in exactly that order.  Thread t owns
+// column t % CH of the chunk and the rows congruent to t / CH; one barrier per
+// elimination step.  CH is a power of two dividing the block size.
+template <int CH>
+__device__ void block_lu_inverse(const double* LU, const int* perm, int r, double* Y, double* Xg) {
+  static_assert((CH & (CH - 1)) == 0 && kThreads % CH == 0, "chunk width");
+  const int tid = threadIdx.x, jj = tid & (CH - 1), g = tid / CH;
+  constexpr int NG = kThreads / CH;
+  for (int j0 = 0; j0 < r; j0 += CH) {
+    const bool act = j0 + jj < r;
+    if (act)
+      for (int i = g; i < r; i += NG) Y[i * CH + jj] = (perm[i] == j0 + jj) ? 1.0 : 0.0;
     __syncthreads();
     for (int k = 0; k < r - 1; ++k) {
-      const int rows = r - k - 1;
-      for (int idx = tid; idx < rows * nch; idx += nt) {
-        const int i = k + 1 + idx / nch, jj = idx % nch;
-        Y[i * ch + jj] = fma(-LU[rowmap[i] * r + k], Y[k * ch + jj], Y[i * ch + jj]);
+      if (act) {
+        const double yk = Y[k * CH + jj];
+        for (int i = k + 1 + g; i < r; i += NG) Y[i * CH + jj] = fma(-LU[i * r + k], yk, Y[i * CH + jj]);
       }
       __syncthreads();
     }
     for (int k = r - 1; k >= 0; --k) {
-      const double ukk = LU[rowmap[k] * r + k];
       // x_k is final once every U(k, k') (k' > k) term has been applied.
-      for (int idx = tid; idx < (k + 1) * nch; idx += nt) {
-        const int i = idx / nch, jj = idx % nch;
-        const double xk = Y[k * ch + jj] / ukk;
-        if (i == k)
-          Xg[(int64_t)k * r + j0 + jj] = xk;
-        else
-          Y[i * ch + jj] = fma(-LU[rowmap[i] * r + k], xk, Y[i * ch + jj]);
+      if (act) {
+        const double xk = Y[k * CH + jj] / LU[k * r + k];
+        if (g == 0) Xg[(int64_t)k * r + j0 + jj] = xk;
+        for (int i = g; i < k; i += NG) Y[i * CH + jj] = fma(-LU[i * r + k], xk, Y[i * CH + jj]);
       }
       __syncthreads();
     }
   }
 }
 
-// The same inverse with one thread per column j and the column held in
-// registers (r <= RMAX <= 64): forward substitution y_i = [rowmap[i] == j] -
-// sum_{k<i} L(i,k) y_k (k ascending), then back substitution
-// x_i = (y_i - sum_{k>i} U(i,k) x_k) / U(i,i) with k descending from r-1 --
-// the per-element operation order of block_lu_inverse, without barriers.
-// LUp: LDS scratch of RMAX*RMAX doubles (position-ordered copy of the factors).
-template <int RMAX>
-__device__ void block_lu_inverse_reg(const double* LU, const int* rowmap, int r, double* LUp,
-                                     double* Xg, double* Xl = nullptr) {
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < r * r; idx += blockDim.x) {
-    const int i = idx / r, k = idx % r;
-    LUp[i * RMAX + k] = LU[rowmap[i] * r + k];
-  }
-  __syncthreads();
-  const int j = tid;
-  if (j < r) {
-    double y[RMAX];
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i) {
-      if (i < r) {
-        double s = (rowmap[i] == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) s = fma(-LUp[i * RMAX + k], y[k], s);
-        y[i] = s;
-      }
-    }
-#pragma unroll
-    for (int i = RMAX - 1; i >= 0; --i) {
-      if (i < r) {
-        double s = y[i];
-#pragma unroll
-        for (int k = RMAX - 1; k > i; --k)
-          if (k < r) s = fma(-LUp[i * RMAX + k], y[k], s);
-        y[i] = s / LUp[i * RMAX + i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i)
-      if (i < r) {
-        Xg[(int64_t)i * r + j] = y[i];
-        if (Xl) Xl[i * r + j] = y[i];
-      }
-  }
-  __syncthreads();
-}
-
 // |det| = prod |U(k,k)| as mant * 2^expo, mant in [0.5,1): frexp split of each
 // factor, one rounded product per step, exact renormalisation.  Thread 0 only.
-__device__ void lu_volume(const double* LU, const int* rowmap, int r, double* mant, int* expo) {
+__device__ void lu_volume(const double* LU, int r, double* mant, int* expo) {
   double mt = 1.0;
   int e = 0;
   for (int k = 0; k < r; ++k) {
     int eu, em;
-    double u = frexp(fabs(LU[rowmap[k] * r + k]), &eu);
+    double u = frexp(fabs(LU[k * r + k]), &eu);
     mt = frexp(mt * u, &em);
     e += eu + em;
   }

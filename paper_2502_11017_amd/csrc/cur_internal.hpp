@@ -63,6 +63,8 @@ struct Node {
   int64_t* I;        // r: selected rows (current order)
   int32_t* Jp;       // r: selected candidate positions (current order)
   double* dbg;       // 4 x kDbgRing swap log (kind, index, slot, pivot) for diagnostics
+  int64_t tclk[8];   // wall-clock ticks spent in controller steps (diagnostics):
+                     // build, col phase, col fresh, col swaps, sort, whole ctl, LU, inverse
   // ---- dynamic state (device) ----
   int32_t nc;        // number of candidates
   int32_t st;        // NodeState

@@ -501,7 +501,7 @@ __device__ void ctl_reduce(Node& nd, CtlLds<T, RMAX>& L) {
 // G = A(I, J) for the current orders, LU, X = G^{-1} to nd.X; optionally the
 // volume instead of X.  Returns false on a singular G.
 template <typename T, int RMAX>
-__device__ bool ctl_build(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_vol) {
+__device__ bool ctl_build_impl(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_vol) {
   const int r = nd.r;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
@@ -510,23 +510,32 @@ __device__ bool ctl_build(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_v
     L.A[idx] = (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
   }
   __syncthreads();
-  if (!block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv)) return false;
-  if (want_vol && threadIdx.x == 0) lu_volume(L.A, L.perm, r, &L.s.vol_m, &L.s.vol_e);
-  if (want_X) {
-    if constexpr (RMAX <= 64)
-      block_lu_inverse_reg<RMAX>(L.A, L.perm, r, L.B, nd.X, L.A);
-    else
-      block_lu_inverse(L.A, L.perm, r, L.B, CtlLds<T, RMAX>::CH, nd.X);
-  }
+  const int64_t tg = wall_clock64();
+  const bool okg = block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv);
+  if (threadIdx.x == 0) nd.tclk[6] += wall_clock64() - tg;
+  if (!okg) return false;
+  if (want_vol && threadIdx.x == 0) lu_volume(L.A, r, &L.s.vol_m, &L.s.vol_e);
+  const int64_t ti = wall_clock64();
+  if (want_X) block_lu_inverse<CtlLds<T, RMAX>::CH>(L.A, L.perm, r, L.B, nd.X);
   __syncthreads();
+  if (threadIdx.x == 0) nd.tclk[7] += wall_clock64() - ti;
   return true;
 }
 
 template <typename T, int RMAX>
+__device__ bool ctl_build(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_vol) {
+  const int64_t t0 = wall_clock64();
+  const bool ok = ctl_build_impl(nd, L, want_X, want_vol);
+  if (threadIdx.x == 0) nd.tclk[0] += wall_clock64() - t0;
+  return ok;
+}
+
+template <typename T, int RMAX>
 __device__ void ctl_sort_IJ(Node& nd, CtlLds<T, RMAX>& L, int n) {
-  (void)nd;
+  const int64_t t0 = wall_clock64();
   block_sort<int64_t>(L.sI, n, L.tmp64);
   block_sort<int32_t>(L.sJp, n, L.tmp32);
+  if (threadIdx.x == 0) nd.tclk[4] += wall_clock64() - t0;
 }
 
 // Fresh column interpolation matrix Bc = X A(I, Jc) (r x nc, row-major, ld ncmax),
@@ -560,20 +569,14 @@ __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
   else block_global_sync();
 }
 
-// X into L.A: the register inverse (r <= 64) already left it there; the LDS
-// inverse wrote it to nd.X only, from which it is read back after the block
-// has published its global stores.
+// X into L.A: the inverse wrote it to nd.X, from which it is read back after
+// the block has published its global stores.
 template <typename T, int RMAX>
 __device__ void ctl_load_X(Node& nd, CtlLds<T, RMAX>& L) {
-  if constexpr (RMAX > 64) {
-    const int r = nd.r;
-    block_global_sync();
-    for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
-    __syncthreads();
-  } else {
-    (void)nd;
-    (void)L;
-  }
+  const int r = nd.r;
+  block_global_sync();
+  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
+  __syncthreads();
 }
 
 // The whole COL phase of one node (maxvol on A(I, Jc)^T with I fixed).
@@ -696,6 +699,7 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
 // swap c* into slot k*: Bc(a,c) = fma(-w_a, Bc(k*,c), Bc(a,c)), column c* := e_k*.
 template <typename T, int RMAX>
 __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
+  const int64_t tph = wall_clock64();
   const int r = nd.r, nc = L.s.nc, tid = threadIdx.x;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
@@ -725,7 +729,7 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   static_assert(RMAX <= 64 && SW == RMAX, "column staging assumes L.B of RMAX x RMAX");
   // fresh Bc: A(I, Jc) is gathered SW columns at a time into L.B (each
   // owner thread issues its r loads back to back), then each owner forms its
-  // column from X (in L.A) with k ascending per element.
+  // column from X (loaded into L.A) with k ascending per element.
 #define CUR_COL_FRESH()                                                        \
   for (int c0 = 0; c0 < nc; c0 += SW) {                                        \
     const bool mine = own && c >= c0 && c < c0 + SW;                           \
@@ -768,10 +772,16 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
     }
     __syncthreads();
   } else {
-    CUR_COL_FRESH();
+    ctl_load_X(nd, L);
+    {
+      const int64_t tf = wall_clock64();
+      CUR_COL_FRESH();
+      if (tid == 0) nd.tclk[2] += wall_clock64() - tf;
+    }
     if (tid == 0) L.s.refreshes++;
     __syncthreads();
     for (int guard = 0;; ++guard) {
+      const int64_t tsw = wall_clock64();
       if (guard >= guard_max) {
         if (tid == 0) L.s.err = 109;
         __syncthreads();
@@ -798,6 +808,7 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
           __syncthreads();
           break;
         }
+        ctl_load_X(nd, L);
         CUR_COL_FRESH();
         if (tid == 0) {
           L.s.refreshes++;
@@ -832,12 +843,14 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
         L.s.swaps++;
         L.s.phase_swaps++;
         L.s.since++;
+        nd.tclk[3] += wall_clock64() - tsw;
       }
       __syncthreads();
     }
   }
   __syncthreads();
 #undef CUR_COL_FRESH
+  if (tid == 0) nd.tclk[1] += wall_clock64() - tph;
   if (tid == 0) {
     L.s.phases++;
     if (L.s.err || L.s.nocap || L.s.phase_swaps == 0) {
@@ -857,6 +870,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
   // the start-up launch only opens swap loops; pass states wait for their pass
   if (startup && nd.st != ST_START_SWAP) return;
   __shared__ CtlLds<T, RMAX> L;
+  const int64_t tctl = wall_clock64();
   const int tid = threadIdx.x;
   const int r = nd.r;
   const int64_t m = nd.m;
@@ -1067,6 +1081,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
   }
   if (tid == 0) {
     const CtlShared& s = L.s;
+    nd.tclk[5] += wall_clock64() - tctl;
     nd.seq = nd.seq + 1;
     nd.st = s.st; nd.t = s.t; nd.q = s.q; nd.na = s.na; nd.steps = s.steps;
     nd.is_short = s.is_short; nd.nocap = s.nocap; nd.err = s.err; nd.phase = s.phase;
@@ -1439,6 +1454,22 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
           }
         }
       }
+  }
+  if (std::getenv("CUR_DEBUG")) {
+    int wclk = 100000;  // ticks per ms of wall_clock64 (100 MHz)
+    hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, ctx->device);  // kHz
+    for (size_t l = 0; l < levels.size(); ++l) {
+      double tsum[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tmax = 0;
+      for (int k = 0; k < levels[l].count; ++k) {
+        const Node& nd = h[levels[l].first + k];
+        for (int q = 0; q < 8; ++q) tsum[q] += nd.tclk[q];
+        tmax = std::max(tmax, (double)nd.tclk[5]);
+      }
+      std::fprintf(stderr, "cur: level %zu nodes %d ctl ms (sum over nodes): build %.2f (lu %.2f inv %.2f) col %.2f "
+                   "colfresh %.2f colswaps %.2f sort %.2f all %.2f; slowest node %.2f\n", l, levels[l].count,
+                   tsum[0] / wclk, tsum[6] / wclk, tsum[7] / wclk, tsum[1] / wclk, tsum[2] / wclk, tsum[3] / wclk,
+                   tsum[4] / wclk, tsum[5] / wclk, tmax / wclk);
+    }
   }
   cur_status result = CUR_OK;
   for (int k = 0; k < total; ++k)
