@@ -30,6 +30,11 @@ __global__ __launch_bounds__(kThreads) void k_gather_R(const T* __restrict__ A, 
     dst[j] = src[j];
 }
 
+template <int RMAX, bool REG = (RMAX <= 64)>
+struct AsmLu : LuScratch {};
+template <int RMAX>
+struct AsmLu<RMAX, false> {};
+
 template <int RMAX>
 struct AsmLds {
   static constexpr int CH = RMAX <= 64 ? RMAX : 16;
@@ -41,6 +46,7 @@ struct AsmLds {
   int pinv;
   double cs[2];
   int rot;
+  AsmLu<RMAX> lu;
 };
 
 // U = A(I,J)^{-1} by LU with partial pivoting, or the Jacobi pseudo-inverse
@@ -52,18 +58,31 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
                                                          double* W, double* V, double* sg, int* flag) {
   __shared__ AsmLds<RMAX> L;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < r * r; idx += kThreads) {
-    const int a = idx / r, b = idx % r;
-    L.A[idx] = (double)A[I[a] * lda + J[b]];
+  // U(k,k) of the factorization: register LU for r <= 64, LDS LU otherwise
+  [[maybe_unused]] LuRegs<(RMAX <= 64 ? RMAX : 64)> R;
+  bool ok;
+  const double* diag;
+  int dstride;
+  if constexpr (RMAX <= 64) {
+    ok = lu_fwd_reg<RMAX>([&](int p, int c) { return (double)A[I[p] * lda + J[c]]; }, r, R, L.B, L.lu);
+    diag = L.lu.diag;
+    dstride = 1;
+  } else {
+    for (int idx = tid; idx < r * r; idx += kThreads) {
+      const int a = idx / r, b = idx % r;
+      L.A[idx] = (double)A[I[a] * lda + J[b]];
+    }
+    __syncthreads();
+    ok = block_gepp(L.A, r, L.perm, L.lk, &L.spiv);
+    diag = L.A;
+    dstride = r + 1;
   }
-  __syncthreads();
-  const bool ok = block_gepp(L.A, r, L.perm, L.lk, &L.spiv);
   if (tid == 0) {
     int use_pinv = 1;
     if (ok) {
       double umin = HUGE_VAL, umax = 0.0;
       for (int k = 0; k < r; ++k) {
-        const double u = fabs(L.A[k * r + k]);
+        const double u = fabs(diag[k * dstride]);
         umin = fmin(umin, u);
         umax = fmax(umax, u);
       }
@@ -74,7 +93,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
   }
   __syncthreads();
   if (!L.pinv) {
-    block_lu_inverse<AsmLds<RMAX>::CH>(L.A, L.perm, r, L.B, U);
+    if constexpr (RMAX <= 64)
+      lu_back_reg<RMAX>(r, R, L.B, L.lu, U, nullptr);
+    else
+      block_lu_inverse<AsmLds<RMAX>::CH>(L.A, L.perm, r, L.B, U);
     return;
   }
   // ---- one-sided Jacobi: W = G V with orthogonal columns (cyclic pairs, <= 60 sweeps)

@@ -190,14 +190,263 @@ __device__ void block_lu_inverse(const double* LU, const int* perm, int r, doubl
   }
 }
 
+// ---------------------------------------------------------------- register LU (r <= 64)
+// LU with partial pivoting and G^{-1} for r <= RMAX <= 64, held in registers:
+// lane p owns row p of G (physical order, never moved), wavefront w owns the
+// columns c = w + 4 j.  Row exchanges are tracked as positions instead of data
+// moves; the arithmetic on every element is that of block_gepp followed by
+// block_lu_inverse (the same operands in the same order), so the results are
+// identical bit for bit:
+//   * the pivot of step k is the largest |G(p,k)| over unpivoted rows, ties to
+//     the smallest position; multipliers l_p = G(p,k) / d;
+//   * G(p,c) = fma(-l_p, G(P,c), G(p,c)) for c > k on unpivoted rows p;
+//   * the forward substitution L y = P e_c rides along as an augmented right
+//     side Y (starting from the identity in physical order), updated with the
+//     same multipliers: row p receives fma(-L(i,k), y_k, .) for k ascending.
+//     Row P of Y is exactly +0 in every column c whose row c has not been
+//     pivoted yet, and an fma with a +0 product leaves a target that is never
+//     -0 unchanged, so those columns are skipped;
+//   * the back substitution runs per wavefront over its own columns of Y,
+//     positions descending, x_k = s / U(k,k).
+// The wavefront owning column k+1 chooses that pivot right after its update,
+// so a step needs one block barrier.  The pivot row is broadcast through a
+// per-wavefront LDS slot (it sits in the same wavefront's registers).
+struct LuScratch {
+  double l[2][64];   // multipliers of the pending step (double-buffered)
+  int info[2];       // pivot row | position << 8 | singular << 16
+  double diag[64];   // U(k,k) in step order
+  int perm[64];      // physical row at position k
+  double xb[4][16];  // per-wavefront staging of one row of X
+  double prow[4][2][16];  // per-wavefront copy of the pivot row (G part, Y part)
+};
+
+template <int RMAX>
+struct LuRegs {
+  static_assert(RMAX == 32 || RMAX == 64, "register LU covers r <= 64");
+  static constexpr int NJ = RMAX / 4;
+  double g[NJ];  // G / LU, columns w + 4 j of row `lane`
+  double y[NJ];  // augmented right side, same columns
+  int pos;       // position of this lane's row
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Largest 64-bit unsigned value over the wavefront, returned uniformly: DPP
+// exchanges inside each 16-lane row (quad xor 1, quad xor 2, half-row mirror,
+// row mirror), then the four row results are combined.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  v = max(v, dpp_u64<0xB1>(v));
+  v = max(v, dpp_u64<0x4E>(v));
+  v = max(v, dpp_u64<0x141>(v));
+  v = max(v, dpp_u64<0x140>(v));
+  return max(max(readlane_u64(v, 0), readlane_u64(v, 16)), max(readlane_u64(v, 32), readlane_u64(v, 48)));
+}
+
+// Order the LDS accesses of one wavefront's lanes around a hand-off.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Pivot of column k chosen by the wavefront that owns it: v = this lane's
+// entry, cand = row not yet pivoted.  Largest |v| first (for |v| >= 0 the bit
+// pattern orders like the value; NaN is no candidate), ties to the smallest
+// position.  Publishes multipliers and pivot to S.
+__device__ __forceinline__ void wave_pivot(double v, bool cand, int pos, int k, int buf, LuScratch& S) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t key = (cand && v == v) ? (uint64_t)__double_as_longlong(fabs(v)) : 0ull;
+  const uint64_t best = wave_max_u64(key);
+  uint64_t tied = __ballot(key == best);
+  int P = (int)__builtin_ctzll(tied);
+  if (tied & (tied - 1)) {  // equal magnitudes: smallest position
+    int bp = 0x7fffffff;
+    while (tied) {
+      const int b = (int)__builtin_ctzll(tied);
+      const int pb = __builtin_amdgcn_readlane(pos, b);
+      if (pb < bp) {
+        bp = pb;
+        P = b;
+      }
+      tied &= tied - 1;
+    }
+  }
+  P = __builtin_amdgcn_readfirstlane(P);
+  const int pp = __builtin_amdgcn_readlane(pos, P);
+  const double d = readlane_f64(v, P);
+  const bool bad = best == 0ull;
+  S.l[buf][lane] = (cand && lane != P && !bad) ? v / d : 0.0;
+  if (lane == 0) {
+    S.info[buf] = P | (pp << 8) | ((bad ? 1 : 0) << 16);
+    S.diag[k] = d;
+    S.perm[k] = P;
+  }
+}
+
+// a[j] for a wavefront-uniform j < NJ (a power of two): a tree of selects on
+// the bits of j, which keeps the array in registers.
+template <int NJ>
+__device__ __forceinline__ double reg_pick(const double (&a)[NJ], int j) {
+  double t[NJ];
+#pragma unroll
+  for (int q = 0; q < NJ; ++q) t[q] = a[q];
+#pragma unroll
+  for (int h = NJ / 2, b = 0; h >= 1; h >>= 1, ++b) {
+    const bool hi = (j >> b) & 1;
+#pragma unroll
+    for (int q = 0; q < h; ++q) t[q] = hi ? t[2 * q + 1] : t[2 * q];
+  }
+  return t[0];
+}
+
+// Factorization and forward substitution.  ldg(p, c) returns G(p, c).  LU is
+// left in R.g and, column-major (element (p, c) at c * RMAX + p, physical
+// rows), in LUl; S.diag / S.perm hold U(k,k) and the row order.  Returns
+// false (uniformly) on a zero pivot.  Ends with a block barrier.
+template <int RMAX, class LoadG>
+__device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, double* LUl, LuScratch& S) {
+  constexpr int NJ = LuRegs<RMAX>::NJ;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool live = lane < r;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int c = w + 4 * j;
+    R.g[j] = (live && c < r) ? ldg(lane, c) : 0.0;
+    R.y[j] = (lane == c) ? 1.0 : 0.0;
+  }
+  R.pos = lane;
+  bool done = !live;
+  uint64_t pivoted = 0;  // physical rows pivoted so far (uniform)
+  if (w == 0) wave_pivot(R.g[0], live, lane, 0, 0, S);
+  for (int k = 0; k < r; ++k) {
+    __syncthreads();
+    const int buf = k & 1;
+    const int info = __builtin_amdgcn_readfirstlane(S.info[buf]);
+    if (info >> 16) return false;
+    const int P = info & 0xff, pp = (info >> 8) & 0xff;
+    const double l = S.l[buf][lane];
+    pivoted |= 1ull << P;
+    const bool upd = !done && lane != P;
+    if (lane == P) {
+      done = true;
+      R.pos = k;
+    } else if (!done && R.pos == k) {
+      R.pos = pp;
+    }
+    // pivot row of this wavefront's columns, broadcast through LDS
+    double* pr = S.prow[w][0];
+    double* pyr = S.prow[w][1];
+    if (lane == P) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        pr[j] = R.g[j];
+        pyr[j] = R.y[j];
+      }
+    }
+    wave_lds_sync();
+    double pg[NJ], py[NJ];  // all loads first: one LDS round trip
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      pg[j] = pr[j];
+      py[j] = pyr[j];
+    }
+    if (upd) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int c = w + 4 * j;
+        if (c == k) R.g[j] = l;
+        if (c > k && c < r) R.g[j] = fma(-l, pg[j], R.g[j]);
+        if (c < r && ((pivoted >> c) & 1)) R.y[j] = fma(-l, py[j], R.y[j]);
+      }
+    }
+    wave_lds_sync();
+    const int k1 = k + 1;
+    if (k1 < r && w == (k1 & 3)) wave_pivot(reg_pick<NJ>(R.g, k1 >> 2), !done, R.pos, k1, buf ^ 1, S);
+  }
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int c = w + 4 * j;
+      if (c < r) LUl[c * RMAX + lane] = R.g[j];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Back substitution after lu_fwd_reg: X = G^{-1}, row-major r x r, written to
+// Xg and/or Xl (either may be null).  Each wavefront works on its own columns
+// without block barriers; the row being divided is staged through S.xb.
+// Ends with a block barrier.
+template <int RMAX>
+__device__ __forceinline__ void lu_back_reg(int r, LuRegs<RMAX>& R, const double* LUl, LuScratch& S, double* Xg,
+                                            double* Xl) {
+  constexpr int NJ = LuRegs<RMAX>::NJ;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int permv = lane < r ? S.perm[lane] : 0;
+  const double diagv = lane < r ? S.diag[lane] : 1.0;
+  double* xb = S.xb[w];
+  const int cl = w + 4 * lane;  // the column this lane divides
+  double u = lane < r ? LUl[(r - 1) * RMAX + lane] : 0.0;  // U(pos, k) of this lane's row
+  for (int k = r - 1; k >= 0; --k) {
+    const int Pk = __builtin_amdgcn_readlane(permv, k);
+    const double dk = readlane_f64(diagv, k);
+    const double un = (k > 0 && lane < r) ? LUl[(k - 1) * RMAX + lane] : 0.0;
+    if (lane == Pk) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) xb[j] = R.y[j];
+    }
+    wave_lds_sync();
+    if (lane < NJ) {
+      const double x = xb[lane] / dk;
+      xb[lane] = x;
+      if (cl < r) {
+        if (Xg) Xg[(int64_t)k * r + cl] = x;
+        if (Xl) Xl[k * r + cl] = x;
+      }
+    }
+    wave_lds_sync();
+    double xk[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) xk[j] = xb[j];
+    if (R.pos < k) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) R.y[j] = fma(-u, xk[j], R.y[j]);
+    }
+    wave_lds_sync();
+    u = un;
+  }
+  __syncthreads();
+}
+
 // |det| = prod |U(k,k)| as mant * 2^expo, mant in [0.5,1): frexp split of each
-// factor, one rounded product per step, exact renormalisation.  Thread 0 only.
-__device__ void lu_volume(const double* LU, int r, double* mant, int* expo) {
+// factor, one rounded product per step, exact renormalisation.  U(k,k) is
+// diag[k * stride].  Thread 0 only.
+__device__ void lu_volume(const double* diag, int stride, int r, double* mant, int* expo) {
   double mt = 1.0;
   int e = 0;
   for (int k = 0; k < r; ++k) {
     int eu, em;
-    double u = frexp(fabs(LU[k * r + k]), &eu);
+    double u = frexp(fabs(diag[k * stride]), &eu);
     mt = frexp(mt * u, &em);
     e += eu + em;
   }

@@ -438,6 +438,12 @@ struct CtlShared {
   Cand win;
 };
 
+// LDS of the register LU, present only where it is used.
+template <int RMAX, bool REG = (RMAX <= 64)>
+struct LuLds : LuScratch {};
+template <int RMAX>
+struct LuLds<RMAX, false> {};
+
 template <typename T, int RMAX>
 struct CtlLds {
   static constexpr int CH = RMAX <= 64 ? RMAX : 16;     // inverse column chunk
@@ -459,6 +465,7 @@ struct CtlLds {
   double rowk[ROWKCAP];
   Cand sc[kThreads / 64];
   CtlShared s;
+  LuLds<RMAX> lu;          // register LU hand-off (r <= 64)
 };
 
 // Append one swap decision to the node's diagnostic ring (thread 0 only).
@@ -498,27 +505,42 @@ __device__ void ctl_reduce(Node& nd, CtlLds<T, RMAX>& L) {
   __syncthreads();
 }
 
-// G = A(I, J) for the current orders, LU, X = G^{-1} to nd.X; optionally the
-// volume instead of X.  Returns false on a singular G.
+// G = A(I, J) for the current orders, LU, X = G^{-1} to nd.X (and, for
+// r <= 64, to L.A); optionally the volume instead of X.  Returns false on a
+// singular G.
 template <typename T, int RMAX>
 __device__ bool ctl_build_impl(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool want_vol) {
   const int r = nd.r;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
-  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
-    const int a = idx / r, b = idx % r;
-    L.A[idx] = (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
+  if constexpr (RMAX <= 64) {
+    const int64_t tg = wall_clock64();
+    LuRegs<RMAX> R;
+    const bool okg = lu_fwd_reg<RMAX>(
+        [&](int p, int c) { return (double)P[(int64_t)L.sJp[c] * m + L.sI[p]]; }, r, R, L.B, L.lu);
+    if (threadIdx.x == 0) nd.tclk[6] += wall_clock64() - tg;
+    if (!okg) return false;
+    if (want_vol && threadIdx.x == 0) lu_volume(L.lu.diag, 1, r, &L.s.vol_m, &L.s.vol_e);
+    const int64_t ti = wall_clock64();
+    if (want_X) lu_back_reg<RMAX>(r, R, L.B, L.lu, nd.X, L.A);
+    __syncthreads();
+    if (threadIdx.x == 0) nd.tclk[7] += wall_clock64() - ti;
+  } else {
+    for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
+      const int a = idx / r, b = idx % r;
+      L.A[idx] = (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
+    }
+    __syncthreads();
+    const int64_t tg = wall_clock64();
+    const bool okg = block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv);
+    if (threadIdx.x == 0) nd.tclk[6] += wall_clock64() - tg;
+    if (!okg) return false;
+    if (want_vol && threadIdx.x == 0) lu_volume(L.A, r + 1, r, &L.s.vol_m, &L.s.vol_e);
+    const int64_t ti = wall_clock64();
+    if (want_X) block_lu_inverse<CtlLds<T, RMAX>::CH>(L.A, L.perm, r, L.B, nd.X);
+    __syncthreads();
+    if (threadIdx.x == 0) nd.tclk[7] += wall_clock64() - ti;
   }
-  __syncthreads();
-  const int64_t tg = wall_clock64();
-  const bool okg = block_gepp(L.A, r, L.perm, L.lk, &L.s.spiv);
-  if (threadIdx.x == 0) nd.tclk[6] += wall_clock64() - tg;
-  if (!okg) return false;
-  if (want_vol && threadIdx.x == 0) lu_volume(L.A, r, &L.s.vol_m, &L.s.vol_e);
-  const int64_t ti = wall_clock64();
-  if (want_X) block_lu_inverse<CtlLds<T, RMAX>::CH>(L.A, L.perm, r, L.B, nd.X);
-  __syncthreads();
-  if (threadIdx.x == 0) nd.tclk[7] += wall_clock64() - ti;
   return true;
 }
 
@@ -569,14 +591,20 @@ __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
   else block_global_sync();
 }
 
-// X into L.A: the inverse wrote it to nd.X, from which it is read back after
-// the block has published its global stores.
+// X into L.A: the register LU (r <= 64) already left it there; the LDS LU
+// wrote it to nd.X only, from which it is read back after the block has
+// published its global stores.
 template <typename T, int RMAX>
 __device__ void ctl_load_X(Node& nd, CtlLds<T, RMAX>& L) {
-  const int r = nd.r;
-  block_global_sync();
-  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
-  __syncthreads();
+  if constexpr (RMAX > 64) {
+    const int r = nd.r;
+    block_global_sync();
+    for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
+    __syncthreads();
+  } else {
+    (void)nd;
+    (void)L;
+  }
 }
 
 // The whole COL phase of one node (maxvol on A(I, Jc)^T with I fixed).
