@@ -392,8 +392,9 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
   return true;
 }
 
-// Back substitution after lu_fwd_reg: X = G^{-1}, row-major r x r, written to
-// Xg and/or Xl (either may be null).  Each wavefront works on its own columns
+// Back substitution after lu_fwd_reg: X = G^{-1}, written row-major r x r to
+// Xg and column-major (element (k, c) at c * RMAX + k) to Xl; either may be
+// null.  Each wavefront works on its own columns
 // without block barriers; the row being divided is staged through S.xb.
 // Ends with a block barrier.
 template <int RMAX>
@@ -421,7 +422,7 @@ __device__ __forceinline__ void lu_back_reg(int r, LuRegs<RMAX>& R, const double
       xb[lane] = x;
       if (cl < r) {
         if (Xg) Xg[(int64_t)k * r + cl] = x;
-        if (Xl) Xl[k * r + cl] = x;
+        if (Xl) Xl[cl * RMAX + k] = x;
       }
     }
     wave_lds_sync();

@@ -560,6 +560,18 @@ __device__ void ctl_sort_IJ(Node& nd, CtlLds<T, RMAX>& L, int n) {
   if (threadIdx.x == 0) nd.tclk[4] += wall_clock64() - t0;
 }
 
+// X(a, k) in L.A: column-major (ld RMAX) from the register LU, row-major (ld r)
+// from the LDS LU.
+template <typename T, int RMAX>
+__device__ __forceinline__ double ctl_x(const CtlLds<T, RMAX>& L, int r, int a, int k) {
+  if constexpr (RMAX <= 64) {
+    (void)r;
+    return L.A[k * RMAX + a];
+  } else {
+    return L.A[a * r + k];
+  }
+}
+
 // Fresh column interpolation matrix Bc = X A(I, Jc) (r x nc, row-major, ld ncmax),
 // sums over k ascending, then column Jp[k] := e_k.  X is in L.A.
 template <typename T, int RMAX>
@@ -578,7 +590,7 @@ __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
     for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
       const int a = idx / nb, j = idx % nb;
       double s = 0.0;
-      for (int k = 0; k < r; ++k) s = fma(L.A[a * r + k], L.B[k * CH + j], s);
+      for (int k = 0; k < r; ++k) s = fma(ctl_x(L, r, a, k), L.B[k * CH + j], s);
       bc[(int64_t)a * ld + c0 + j] = s;
     }
     __syncthreads();
@@ -720,21 +732,31 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   __syncthreads();
 }
 
-// The COL phase with one thread per candidate column: thread c (< nc <=
-// kThreads) owns column c of Bc, stored in LDS with leading dimension nc
-// (r * nc <= BCCAP).  Same decisions and per-element arithmetic as
-// ctl_col_phase: fresh Bc(a,c) = sum_k X(a,k) A(I[k],Jc[c]) with k ascending;
-// swap c* into slot k*: Bc(a,c) = fma(-w_a, Bc(k*,c), Bc(a,c)), column c* := e_k*.
+// The COL phase for r <= 64 and r < nc <= 128 with Bc in registers: lane a
+// holds row a of Bc, wavefront w the columns c = w + 4 j (j < 32).  Same
+// arithmetic as ctl_col_phase, element by element:
+//   fresh  Bc(a,c) = sum_k X(a,k) A(I_k, Jc_c), k ascending, columns in J := e_k;
+//   argmax over columns not in J, larger |Bc| first, ties to the smaller
+//          column-major key c * r + a;
+//   swap   p = Bc(ks,cs); v_a = Bc(a,cs)/p (a != ks), v_ks = (p-1)/p;
+//          Bc(a,c) = fma(-v_a, Bc(ks,c), Bc(a,c)) for every c; column cs := e_ks.
+// A(I, Jc) is staged in L.Bcl row by row, each wavefront's 32 columns
+// contiguous (element (k, c) at k * 128 + (c & 3) * 32 + (c >> 2)).
 template <typename T, int RMAX>
-__device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
+__device__ void ctl_col_phase_reg(Node& nd, CtlLds<T, RMAX>& L, double lim) {
+  static_assert(RMAX <= 64, "register column phase needs r <= 64");
+  static_assert(CtlLds<T, RMAX>::BCCAP >= 64 * 128, "A(I, Jc) staging");
+  constexpr int NCJ = 32;
   const int64_t tph = wall_clock64();
-  const int r = nd.r, nc = L.s.nc, tid = threadIdx.x;
+  const int r = nd.r, nc = L.s.nc, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
   const int guard_max = 4 * nd.smax + 16;
   uint8_t* insel = L.insel;
-  double* bc = L.Bcl;  // r x nc, element (a, c) at a * nc + c
   int* slot = L.slot;
+  double* Ag = L.Bcl;
+  double* prow = L.rowk + w * NCJ;  // this wavefront's copy of row ks
   ctl_sort_IJ(nd, L, r);
   if (tid == 0) {
     L.s.phase_swaps = 0;
@@ -750,41 +772,47 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
     slot[L.sJp[k]] = k;
   }
   __syncthreads();
-  const int c = tid;
-  const bool own = c < nc;
-  constexpr int AC = 16;  // rows of a column accumulated per sweep over k
-  constexpr int SW = CtlLds<T, RMAX>::CH;  // columns staged per chunk (L.B is RMAX x SW)
-  static_assert(RMAX <= 64 && SW == RMAX, "column staging assumes L.B of RMAX x RMAX");
-  // fresh Bc: A(I, Jc) is gathered SW columns at a time into L.B (each
-  // owner thread issues its r loads back to back), then each owner forms its
-  // column from X (loaded into L.A) with k ascending per element.
-#define CUR_COL_FRESH()                                                        \
-  for (int c0 = 0; c0 < nc; c0 += SW) {                                        \
-    const bool mine = own && c >= c0 && c < c0 + SW;                           \
-    if (mine) {                                                                \
-      const T* col = P + (int64_t)c * m;                                       \
-      _Pragma("unroll 8") for (int k = 0; k < r; ++k)                          \
-        L.B[k * SW + (c - c0)] = (double)col[L.sI[k]];                         \
-    }                                                                          \
-    __syncthreads();                                                           \
-    if (mine) {                                                                \
-      for (int a0 = 0; a0 < r; a0 += AC) {                                     \
-        double acc[AC];                                                        \
-        _Pragma("unroll") for (int j = 0; j < AC; ++j) acc[j] = 0.0;           \
-        for (int k = 0; k < r; ++k) {                                          \
-          const double pk = L.B[k * SW + (c - c0)];                            \
-          _Pragma("unroll") for (int j = 0; j < AC; ++j)                       \
-            if (a0 + j < r) acc[j] = fma(L.A[(a0 + j) * r + k], pk, acc[j]);   \
-        }                                                                      \
-        _Pragma("unroll") for (int j = 0; j < AC; ++j)                         \
-          if (a0 + j < r) bc[(a0 + j) * nc + c] = acc[j];                      \
-      }                                                                        \
-      const int sl = slot[c];                                                  \
-      if (sl >= 0)                                                             \
-        for (int a = 0; a < r; ++a) bc[a * nc + c] = (a == sl) ? 1.0 : 0.0;    \
-    }                                                                          \
-    __syncthreads();                                                           \
+  uint32_t inJ = 0;  // bit j: column w + 4 j is in J (uniform)
+#pragma unroll
+  for (int j = 0; j < NCJ; ++j) {
+    const int c = w + 4 * j;
+    if (c < nc && insel[c]) inJ |= 1u << j;
   }
+  double bcr[NCJ];
+  // fresh Bc from X (L.A, column-major) and A(I, Jc)
+  auto fresh = [&]() {
+    const int64_t tf = wall_clock64();
+    {
+      const int c = tid & 127;
+      double v[32];
+#pragma unroll
+      for (int q = 0; q < 32; ++q) {
+        const int k = (tid >> 7) + 2 * q;
+        v[q] = (c < nc && k < r) ? (double)P[(int64_t)c * m + L.sI[k]] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 32; ++q) {
+        const int k = (tid >> 7) + 2 * q;
+        if (k < r) Ag[k * 128 + (c & 3) * NCJ + (c >> 2)] = v[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NCJ; ++j) bcr[j] = 0.0;
+    const double* Arow = Ag + w * NCJ;
+    for (int k = 0; k < r; ++k) {
+      const double xa = L.A[k * RMAX + lane];
+      double av[NCJ];
+#pragma unroll
+      for (int j = 0; j < NCJ; ++j) av[j] = Arow[k * 128 + j];
+#pragma unroll
+      for (int j = 0; j < NCJ; ++j) bcr[j] = fma(xa, av[j], bcr[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NCJ; ++j)
+      if ((inJ >> j) & 1) bcr[j] = (lane == slot[w + 4 * j]) ? 1.0 : 0.0;
+    if (tid == 0) nd.tclk[2] += wall_clock64() - tf;
+  };
   if (!ctl_build(nd, L, true, false)) {
     if (tid == 0) {
       int code = 108;  // numerically singular cross
@@ -800,12 +828,7 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
     }
     __syncthreads();
   } else {
-    ctl_load_X(nd, L);
-    {
-      const int64_t tf = wall_clock64();
-      CUR_COL_FRESH();
-      if (tid == 0) nd.tclk[2] += wall_clock64() - tf;
-    }
+    fresh();
     if (tid == 0) L.s.refreshes++;
     __syncthreads();
     for (int guard = 0;; ++guard) {
@@ -815,20 +838,59 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
         __syncthreads();
         break;
       }
-      Cand b = cand_none();
-      if (own && !insel[c]) {
-        for (int a = 0; a < r; ++a) {
-          const double x = bc[a * nc + c];
-          Cand o;
-          o.val = fabs(x);
-          o.sval = x;
-          o.key = (int64_t)c * r + a;
-          o.row = a;
-          o.pos = c;
-          cand_take(b, o);
+      // ---- argmax: per lane over its columns (c ascending), then the wavefront, then the block
+      uint64_t bkey = 0;  // bits of |Bc| (monotone for |x| >= 0); 0: none
+      int bj = 0;
+      double bsv = 0.0;
+      if (lane < r) {
+#pragma unroll
+        for (int j = 0; j < NCJ; ++j) {
+          const int c = w + 4 * j;
+          if (c < nc && !((inJ >> j) & 1)) {
+            const double x = bcr[j];
+            const uint64_t u = (x == x) ? (uint64_t)__double_as_longlong(fabs(x)) : 0ull;
+            if (u > bkey) {
+              bkey = u;
+              bj = j;
+              bsv = x;
+            }
+          }
         }
       }
-      b = block_argmax(b, L.sc);
+      const uint64_t wbest = wave_max_u64(bkey);
+      uint64_t tied = __ballot(bkey == wbest && wbest != 0ull);
+      if (wbest != 0ull) {
+        int win = (int)__builtin_ctzll(tied);
+        if (tied & (tied - 1)) {
+          int64_t kbest = INT64_MAX;
+          while (tied) {
+            const int b = (int)__builtin_ctzll(tied);
+            const int64_t kb = (int64_t)(w + 4 * __builtin_amdgcn_readlane(bj, b)) * r + b;
+            if (kb < kbest) {
+              kbest = kb;
+              win = b;
+            }
+            tied &= tied - 1;
+          }
+        }
+        win = __builtin_amdgcn_readfirstlane(win);
+        if (lane == win) {
+          Cand o;
+          o.val = fabs(bsv);
+          o.sval = bsv;
+          o.pos = w + 4 * bj;
+          o.row = lane;
+          o.key = (int64_t)o.pos * r + lane;
+          L.sc[w] = o;
+        }
+      } else if (lane == 0) {
+        L.sc[w] = cand_none();
+      }
+      __syncthreads();
+      Cand b = L.sc[0];
+#pragma unroll
+      for (int q = 1; q < kThreads / 64; ++q) cand_take(b, L.sc[q]);
+      __syncthreads();  // L.sc is rewritten by the next argmax
       if (b.row < 0 || b.val <= lim) {
         if (L.s.since == 0) break;
         if (!ctl_build(nd, L, true, false)) {
@@ -836,8 +898,7 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
           __syncthreads();
           break;
         }
-        ctl_load_X(nd, L);
-        CUR_COL_FRESH();
+        fresh();
         if (tid == 0) {
           L.s.refreshes++;
           L.s.since = 0;
@@ -850,19 +911,36 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
         __syncthreads();
         break;
       }
+      // ---- swap column cs into slot ks
       const int ks = (int)b.row, cs = b.pos;
       const double p = b.sval;
-      for (int a = tid; a < r; a += kThreads) L.wv[a] = (a == ks) ? (p - 1.0) / p : bc[a * nc + cs] / p;
-      __syncthreads();
-      if (own) {
-        const double rk = bc[ks * nc + c];
-        for (int a = 0; a < r; ++a) bc[a * nc + c] = fma(-L.wv[a], rk, bc[a * nc + c]);
-        if (c == cs)
-          for (int a = 0; a < r; ++a) bc[a * nc + c] = (a == ks) ? 1.0 : 0.0;
+      if (w == (cs & 3) && lane < r) {
+        const double col = reg_pick<NCJ>(bcr, cs >> 2);
+        L.wv[lane] = (lane == ks) ? (p - 1.0) / p : col / p;
       }
+      if (lane == ks) {
+#pragma unroll
+        for (int j = 0; j < NCJ; ++j) prow[j] = bcr[j];
+      }
+      __syncthreads();
+      {
+        double rk[NCJ];
+#pragma unroll
+        for (int j = 0; j < NCJ; ++j) rk[j] = prow[j];
+        const double va = lane < r ? L.wv[lane] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NCJ; ++j) {
+          const int c = w + 4 * j;
+          if (c < nc) bcr[j] = fma(-va, rk[j], bcr[j]);
+          if (c == cs) bcr[j] = (lane == ks) ? 1.0 : 0.0;
+        }
+      }
+      const int old = L.sJp[ks];
+      if ((old & 3) == w) inJ &= ~(1u << (old >> 2));
+      if ((cs & 3) == w) inJ |= 1u << (cs >> 2);
+      __syncthreads();  // every wavefront has read L.sJp, prow and L.wv
       if (tid == 0) {
         dbg_log(nd, L.s.swaps, 2.0 + 0.001 * L.s.refreshes, (double)cs, (double)ks, p);
-        const int old = L.sJp[ks];
         insel[old] = 0;
         slot[old] = -1;
         insel[cs] = 1;
@@ -877,7 +955,6 @@ __device__ void ctl_col_phase_cols(Node& nd, CtlLds<T, RMAX>& L, double lim) {
     }
   }
   __syncthreads();
-#undef CUR_COL_FRESH
   if (tid == 0) nd.tclk[1] += wall_clock64() - tph;
   if (tid == 0) {
     L.s.phases++;
@@ -1064,8 +1141,8 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
       __syncthreads();
     } else if (mode == M_COL) {
       if constexpr (RMAX <= 64) {
-        if (L.s.nc <= kThreads && L.s.nc > r && r * L.s.nc <= CtlLds<T, RMAX>::BCCAP)
-          ctl_col_phase_cols(nd, L, lim);
+        if (L.s.nc > r && L.s.nc <= 128)
+          ctl_col_phase_reg(nd, L, lim);
         else
           ctl_col_phase(nd, L, lim);
       } else {
