@@ -194,32 +194,33 @@ __device__ void block_lu_inverse(const double* LU, const int* perm, int r, doubl
 // LU with partial pivoting and G^{-1} for r <= RMAX <= 64, held in registers:
 // lane p owns row p of G (physical order, never moved), wavefront w owns the
 // columns c = w + 4 j.  Row exchanges are tracked as positions instead of data
-// moves; the arithmetic on every element is that of block_gepp followed by
-// block_lu_inverse (the same operands in the same order), so the results are
-// identical bit for bit:
+// moves.  Every value that reaches U, X or the volume is computed with the
+// operands and in the order of block_gepp followed by block_lu_inverse, so the
+// results are identical bit for bit:
 //   * the pivot of step k is the largest |G(p,k)| over unpivoted rows, ties to
 //     the smallest position; multipliers l_p = G(p,k) / d;
 //   * G(p,c) = fma(-l_p, G(P,c), G(p,c)) for c > k on unpivoted rows p;
 //   * the forward substitution L y = P e_c rides along as an augmented right
 //     side Y (starting from the identity in physical order), updated with the
-//     same multipliers: row p receives fma(-L(i,k), y_k, .) for k ascending.
-//     Row P of Y is exactly +0 in every column c whose row c has not been
-//     pivoted yet, and an fma with a +0 product leaves a target that is never
-//     -0 unchanged, so those columns are skipped;
+//     same multipliers: row p receives fma(-L(i,k), y_k, .) for k ascending;
 //   * the back substitution runs per wavefront over its own columns of Y,
 //     positions descending, x_k = s / U(k,k).
-// The wavefront owning column k+1 chooses that pivot right after its update,
-// so a step needs one block barrier.  The pivot row is broadcast through a
-// per-wavefront LDS slot (it sits in the same wavefront's registers).
+// With Y carried along, the multipliers are dead once their step is done (the
+// back substitution reads U only), so a step updates every column of the
+// unpivoted rows without testing c > k: the L part is left as scratch.  In Y,
+// row P is exactly +0 in every column c whose row c is not yet pivoted, and an
+// fma with a +0 product leaves a target that is never -0 unchanged.
+// The wavefront owning column k+1 updates that column first, chooses its
+// pivot and publishes it before its bulk update, so a step needs one block
+// barrier.  The pivot row of a wavefront's columns is broadcast through LDS.
 struct LuScratch {
-  double l[2][64];   // multipliers of the pending step (double-buffered)
-  int info[2];       // pivot row | position << 8 | singular << 16
-  double diag[64];   // U(k,k) in step order
-  int perm[64];      // physical row at position k
-  double xb[4][16];  // per-wavefront staging of one row of X
+  double l[2][64];        // multipliers of the pending step (double-buffered)
+  int info[2];            // pivot row | position << 8 | singular << 16
+  double diag[64];        // U(k,k) in step order
+  int perm[64];           // physical row at position k
+  double xb[4][16];       // per-wavefront staging of one row of X
   double prow[4][2][16];  // per-wavefront copy of the pivot row (G part, Y part)
 };
-
 template <int RMAX>
 struct LuRegs {
   static_assert(RMAX == 32 || RMAX == 64, "register LU covers r <= 64");
@@ -316,10 +317,11 @@ __device__ __forceinline__ double reg_pick(const double (&a)[NJ], int j) {
   return t[0];
 }
 
-// Factorization and forward substitution.  ldg(p, c) returns G(p, c).  LU is
+// Factorization and forward substitution.  ldg(p, c) returns G(p, c).  U is
 // left in R.g and, column-major (element (p, c) at c * RMAX + p, physical
-// rows), in LUl; S.diag / S.perm hold U(k,k) and the row order.  Returns
-// false (uniformly) on a zero pivot.  Ends with a block barrier.
+// rows; entries left of a row's pivot are scratch), in LUl; S.diag / S.perm
+// hold U(k,k) and the row order.  Returns false (uniformly) on a zero pivot.
+// Ends with a block barrier.
 template <int RMAX, class LoadG>
 __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, double* LUl, LuScratch& S) {
   constexpr int NJ = LuRegs<RMAX>::NJ;
@@ -334,16 +336,20 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
   }
   R.pos = lane;
   bool done = !live;
-  uint64_t pivoted = 0;  // physical rows pivoted so far (uniform)
   if (w == 0) wave_pivot(R.g[0], live, lane, 0, 0, S);
+  double* pr = S.prow[w][0];
+  double* pyr = S.prow[w][1];
   for (int k = 0; k < r; ++k) {
+    const int k1 = k + 1;
+    const bool owner = k1 < r && w == (k1 & 3);
+    double cv = 0.0;
+    if (owner) cv = reg_pick<NJ>(R.g, k1 >> 2);  // column k+1 before this step
     __syncthreads();
     const int buf = k & 1;
     const int info = __builtin_amdgcn_readfirstlane(S.info[buf]);
     if (info >> 16) return false;
     const int P = info & 0xff, pp = (info >> 8) & 0xff;
     const double l = S.l[buf][lane];
-    pivoted |= 1ull << P;
     const bool upd = !done && lane != P;
     if (lane == P) {
       done = true;
@@ -351,9 +357,12 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
     } else if (!done && R.pos == k) {
       R.pos = pp;
     }
-    // pivot row of this wavefront's columns, broadcast through LDS
-    double* pr = S.prow[w][0];
-    double* pyr = S.prow[w][1];
+    if (owner) {
+      const double pc = readlane_f64(cv, P);
+      if (upd) cv = fma(-l, pc, cv);
+      wave_pivot(cv, !done, R.pos, k1, buf ^ 1, S);
+    }
+    // bulk update of this wavefront's columns
     if (lane == P) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -362,7 +371,7 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
       }
     }
     wave_lds_sync();
-    double pg[NJ], py[NJ];  // all loads first: one LDS round trip
+    double pg[NJ], py[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       pg[j] = pr[j];
@@ -371,15 +380,11 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
     if (upd) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const int c = w + 4 * j;
-        if (c == k) R.g[j] = l;
-        if (c > k && c < r) R.g[j] = fma(-l, pg[j], R.g[j]);
-        if (c < r && ((pivoted >> c) & 1)) R.y[j] = fma(-l, py[j], R.y[j]);
+        R.g[j] = fma(-l, pg[j], R.g[j]);
+        R.y[j] = fma(-l, py[j], R.y[j]);
       }
     }
     wave_lds_sync();
-    const int k1 = k + 1;
-    if (k1 < r && w == (k1 & 3)) wave_pivot(reg_pick<NJ>(R.g, k1 >> 2), !done, R.pos, k1, buf ^ 1, S);
   }
   if (live) {
 #pragma unroll

@@ -231,6 +231,23 @@ __global__ __launch_bounds__(kThreads) void k_panel_build(Node* nodes, const Nod
 // ACA step, fresh B, or row swap over one tile of kTileRows rows, fused with the
 // tile's argmax.  Writes the tile winner and its full row (in the layout the
 // next step reads) to the node's partial arrays.
+// Best candidate of one row scanned in ascending column order (key row * r + c):
+// the first strictly larger |x| wins, NaN never does.  Compares the bit
+// pattern of |x|, which orders like the value for |x| >= 0.
+struct RowBest {
+  uint64_t bits = 0;
+  double x = 0.0;
+  int c = -1;
+  __device__ __forceinline__ void take(double v, int col) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
+    if (v == v && (c < 0 || u > bits)) {
+      bits = u;
+      x = v;
+      c = col;
+    }
+  }
+};
+
 template <typename T, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long long* prof) {
   Node& nd = nodes[blockIdx.y];
@@ -313,6 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
     }
     __syncthreads();
     const int slot = sslot[tid];
+    RowBest rb;
     if (st == ST_ROW_FRESH) {
       for (int c0 = 0; c0 < r; c0 += CB) {
         const int nb = min(CB, r - c0);
@@ -345,15 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
             T b = (T)acc[j];
             if (slot >= 0) b = (c == slot) ? (T)1 : (T)0;
             W[(int64_t)c * m + row] = b;
-            if (slot < 0) {
-              Cand o;
-              o.val = fabs((double)b);
-              o.sval = (double)b;
-              o.key = row * r + c;
-              o.row = row;
-              o.pos = c;
-              cand_take(best, o);
-            }
+            if (slot < 0) rb.take((double)b, c);
           }
         }
       }
@@ -375,18 +385,17 @@ __global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long lo
             T b = fma_t<T>(-g, (T)v[c], bs[u]);
             if (row == is) b = (c == ks) ? (T)1 : (T)0;
             W[(int64_t)c * m + row] = b;
-            if (slot < 0) {
-              Cand o;
-              o.val = fabs((double)b);
-              o.sval = (double)b;
-              o.key = row * r + c;
-              o.row = row;
-              o.pos = c;
-              cand_take(best, o);
-            }
+            if (slot < 0) rb.take((double)b, c);
           }
         }
       }
+    }
+    if (rb.c >= 0) {
+      best.val = fabs(rb.x);
+      best.sval = rb.x;
+      best.key = row * r + rb.c;
+      best.row = row;
+      best.pos = rb.c;
     }
   }
 
