@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_c2_traffic.json")
-PASS_SOURCE = os.path.join(ROOT, "paper_2502_11017_amd", "csrc", "select.hip")
+PASS_SOURCE = os.path.join(ROOT, "paper_2502_11017_amd", "csrc", "pass.hip")
 
 
 def log(msg):
@@ -65,6 +65,11 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
+    ap.add_argument("--host-matrix", action="store_true",
+                    help="build the C2 matrix on the host and copy it over (for counter runs)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="one untimed device copy of this size, the calibration of the byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -80,9 +85,20 @@ def main():
     dev = torch.device("cuda:0")
     m = n = 8192
     r = 64
-    log(f"generating C2 {m}x{n} seed {args.seed} on the GPU")
-    A = W.c2(args.seed, device=dev, n=n)
+    if args.host_matrix:
+        log(f"generating C2 {m}x{n} seed {args.seed} on the host")
+        A = W.c2(args.seed, device="cpu", n=n).to(dev)
+    else:
+        log(f"generating C2 {m}x{n} seed {args.seed} on the GPU")
+        A = W.c2(args.seed, device=dev, n=n)
     torch.cuda.synchronize()
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {src.numel() * 8} bytes read and written")
+        del src, dst
 
     def step(Ax):
         res = cur.select(Ax, r)
@@ -121,10 +137,15 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - a) / reps, out
 
-    t_sel, res = timed(lambda: cur.select(A, r))
-    t_asm, (C, U, R) = timed(lambda: cur.assemble(A, res["I"], res["J"]))
-    t_res, (cheb, fro) = timed(lambda: cur.residual(A, C, U, R))
-    res_tflops = 2.0 * m * n * r / t_res / 1e12
+    if args.no_stages:
+        t_sel = t_asm = t_res = None
+        C, U, R = cur.assemble(A, res["I"], res["J"])
+        res_tflops = None
+    else:
+        t_sel, res = timed(lambda: cur.select(A, r))
+        t_asm, (C, U, R) = timed(lambda: cur.assemble(A, res["I"], res["J"]))
+        t_res, (cheb, fro) = timed(lambda: cur.residual(A, C, U, R))
+        res_tflops = 2.0 * m * n * r / t_res / 1e12
 
     pass_gbs = prof["bytes"] / prof["seconds"] / 1e9 if prof["seconds"] > 0 else 0.0
     launches = max(prof["launches"], 1)
@@ -193,9 +214,10 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "launches_per_step": prof["launches"] / max(args.steps, 1),
                      "avg_launch_us": 1e6 * prof["seconds"] / launches},
-        "stages_ms": {"select": 1e3 * t_sel, "assemble": 1e3 * t_asm, "residual": 1e3 * t_res},
+        "stages_ms": None if args.no_stages else {"select": 1e3 * t_sel, "assemble": 1e3 * t_asm,
+                                                  "residual": 1e3 * t_res},
         "residual": {"cheb": cheb, "fro_rel": fro, "tflops": res_tflops,
-                     "frac_fp64_peak": res_tflops / FP64_PEAK_TFLOPS},
+                     "frac_fp64_peak": None if res_tflops is None else res_tflops / FP64_PEAK_TFLOPS},
         "selection": {"status": res["status"], "swaps": res["swaps"], "phases": res["phases"],
                       "refreshes": res["refreshes"], "nodes": res["nodes"], "logvol": res["logvol"]},
         "f32": f32,

@@ -130,6 +130,10 @@ struct Arena {
 };
 cur_status ensure_arena(cur_ctx ctx, size_t bytes);
 
+// One row pass over every active node of a level (pass.hip); rb is the
+// register bucket of r (32, 64 or 128), prof the device byte counter or null.
+void pass_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
+
 cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                            int64_t lda, int r, const cur_opts& o, int64_t* I, int64_t* J,
                            cur_info* info);

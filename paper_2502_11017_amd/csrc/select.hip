@@ -4,14 +4,15 @@
 //
 // Execution model.  A tree level is a table of nodes.  The host repeats two
 // launches until every node of the level is finished:
-//   k_pass  grid (row tiles x nodes): the bandwidth-bound sweep over a node's
-//           m x (active columns) working matrix -- an ACA rank-1 update, a row
-//           swap (Sherman-Morrison) update, or a fresh B = A(:,J) A(I,J)^-1 --
-//           fused with the per-tile argmax of the next decision;
+//   k_pass  grid (row tiles x nodes), in pass.hip: the bandwidth-bound sweep
+//           over a node's m x (active columns) working matrix -- an ACA rank-1
+//           update, a row swap (Sherman-Morrison) update, or a fresh
+//           B = A(:,J) A(I,J)^-1 -- fused with the per-tile argmax of the next
+//           decision;
 //   k_ctl   one workgroup per node: reduces the tile winners (the global
 //           maximum of Alg. 3), takes the decision of the documented algorithm
-//           and does the small serial work (r x r LU in LDS, inverse, the
-//           column phase on the r x |Jc| matrix, sorting, the final volume).
+//           and does the small serial work (r x r LU and inverse, the column
+//           phase on the r x |Jc| matrix, sorting, the final volume).
 // No kernel waits on another workgroup, so every launch ends by construction;
 // the host bounds the number of iterations.
 //
@@ -25,6 +26,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "cur_device.hpp"
@@ -225,199 +227,6 @@ __global__ __launch_bounds__(kThreads) void k_panel_build(Node* nodes, const Nod
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nd.m;
        i += (int64_t)gridDim.x * kThreads)
     dst[i] = src[i];
-}
-
-// ---------------------------------------------------------------- the pass
-// ACA step, fresh B, or row swap over one tile of kTileRows rows, fused with the
-// tile's argmax.  Writes the tile winner and its full row (in the layout the
-// next step reads) to the node's partial arrays.
-// Best candidate of one row scanned in ascending column order (key row * r + c):
-// the first strictly larger |x| wins, NaN never does.  Compares the bit
-// pattern of |x|, which orders like the value for |x| >= 0.
-struct RowBest {
-  uint64_t bits = 0;
-  double x = 0.0;
-  int c = -1;
-  __device__ __forceinline__ void take(double v, int col) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
-    if (v == v && (c < 0 || u > bits)) {
-      bits = u;
-      x = v;
-      c = col;
-    }
-  }
-};
-
-template <typename T, int RMAX>
-__global__ __launch_bounds__(kThreads) void k_pass(Node* nodes, unsigned long long* prof) {
-  Node& nd = nodes[blockIdx.y];
-  const int st = nd.st;
-  if (st != ST_ACA && st != ST_ROW_FRESH && st != ST_ROW_SWAP) return;
-  const int tile = blockIdx.x;
-  if (tile >= nd.ntiles) return;
-  const int64_t m = nd.m;
-  const int r = nd.r;
-  const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)tile * kTileRows;
-  const int64_t row = row0 + tid;
-  const bool valid = row < m;
-  T* W = (T*)nd.work;
-  const T* P = (const T*)nd.panel;
-
-  constexpr int CB = 16;  // columns of X staged per chunk (fresh B)
-  __shared__ double sX[RMAX * CB];
-  __shared__ int sJp[RMAX];
-  __shared__ int sslot[kTileRows];
-  __shared__ Cand sc[kThreads / 64];
-
-  Cand best = cand_none();
-
-  if (st == ST_ACA) {
-    const int t = nd.t, na = nd.na, nc = nd.nc;
-    const int32_t* cmap = nd.colmap;
-    const T* src = (t <= 1) ? P : W;
-    if (t == 0) {
-      if (valid)
-#pragma unroll 8
-        for (int c = 0; c < na; ++c) {
-          const T x = src[(int64_t)c * m + row];
-          Cand o;
-          o.val = fabs((double)x);
-          o.sval = (double)x;
-          o.key = row * nc + cmap[c];
-          o.row = row;
-          o.pos = c;
-          cand_take(best, o);
-        }
-    } else {
-      const int pc = nd.pend_k;
-      const int64_t pi = nd.pend_i;
-      const double* f = nd.vec;
-      if (valid) {
-        const T g = src[(int64_t)pc * m + row];
-        constexpr int U = 8;  // independent loads in flight per lane
-        for (int c0 = 0; c0 < na; c0 += U) {
-          T xs[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) xs[u] = (c0 + u < na) ? src[(int64_t)(c0 + u) * m + row] : (T)0;
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int c = c0 + u;
-            if (c >= na || c == pc) continue;
-            T x = fma_t<T>(-g, (T)f[c], xs[u]);
-            if (row == pi) x = (T)0;
-            const int np = (c == na - 1) ? pc : c;
-            W[(int64_t)np * m + row] = x;
-            Cand o;
-            o.val = fabs((double)x);
-            o.sval = (double)x;
-            o.key = row * nc + cmap[c];
-            o.row = row;
-            o.pos = np;
-            cand_take(best, o);
-          }
-        }
-      }
-    }
-  } else {
-    // masked rows: the selected ones, with their slot k
-    sslot[tid] = -1;
-    __syncthreads();
-    for (int k = tid; k < r; k += kThreads) {
-      const int64_t i = nd.I[k];
-      if (i >= row0 && i < row0 + kTileRows) sslot[i - row0] = k;
-      sJp[k] = nd.Jp[k];
-    }
-    __syncthreads();
-    const int slot = sslot[tid];
-    RowBest rb;
-    if (st == ST_ROW_FRESH) {
-      for (int c0 = 0; c0 < r; c0 += CB) {
-        const int nb = min(CB, r - c0);
-        __syncthreads();
-        for (int idx = tid; idx < r * CB; idx += kThreads) {
-          const int k = idx / CB, j = idx % CB;
-          sX[idx] = (j < nb) ? nd.X[(int64_t)k * r + c0 + j] : 0.0;
-        }
-        __syncthreads();
-        if (valid) {
-          double acc[CB];
-#pragma unroll
-          for (int j = 0; j < CB; ++j) acc[j] = 0.0;
-          constexpr int U = 8;
-          for (int k0 = 0; k0 < r; k0 += U) {
-            double pk[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) pk[u] = (k0 + u < r) ? (double)P[(int64_t)sJp[k0 + u] * m + row] : 0.0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              if (k0 + u >= r) break;
-#pragma unroll
-              for (int j = 0; j < CB; ++j) acc[j] = fma(pk[u], sX[(k0 + u) * CB + j], acc[j]);
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            if (j >= nb) break;
-            const int c = c0 + j;
-            T b = (T)acc[j];
-            if (slot >= 0) b = (c == slot) ? (T)1 : (T)0;
-            W[(int64_t)c * m + row] = b;
-            if (slot < 0) rb.take((double)b, c);
-          }
-        }
-      }
-    } else {
-      const int ks = nd.pend_k;
-      const int64_t is = nd.pend_i;
-      const double* v = nd.vec;
-      if (valid) {
-        const T g = W[(int64_t)ks * m + row];
-        constexpr int U = 8;
-        for (int c0 = 0; c0 < r; c0 += U) {
-          T bs[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) bs[u] = (c0 + u < r) ? W[(int64_t)(c0 + u) * m + row] : (T)0;
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int c = c0 + u;
-            if (c >= r) continue;
-            T b = fma_t<T>(-g, (T)v[c], bs[u]);
-            if (row == is) b = (c == ks) ? (T)1 : (T)0;
-            W[(int64_t)c * m + row] = b;
-            if (slot < 0) rb.take((double)b, c);
-          }
-        }
-      }
-    }
-    if (rb.c >= 0) {
-      best.val = fabs(rb.x);
-      best.sval = rb.x;
-      best.key = row * r + rb.c;
-      best.row = row;
-      best.pos = rb.c;
-    }
-  }
-
-  best = block_argmax(best, sc);
-  if (prof && tid == 0) {
-    // algorithmic bytes of this tile: working columns read + columns written
-    const int64_t rows = min((int64_t)kTileRows, m - row0);
-    int64_t cols;
-    if (st == ST_ACA) cols = (nd.t == 0) ? nd.na : 2 * nd.na - 1;
-    else cols = 2 * (int64_t)r;
-    atomicAdd(prof, (unsigned long long)(rows * cols * (int64_t)sizeof(T)));
-  }
-  if (tid == 0) {
-    Partial p;
-    p.val = best.val;
-    p.sval = best.sval;
-    p.key = best.key;
-    p.row = best.row;
-    p.pos = best.pos;
-    p.seq = nd.seq;
-    nd.part[tile] = p;
-  }
 }
 
 // ---------------------------------------------------------------- the controller
@@ -1242,19 +1051,13 @@ struct SelectPlan {
 static int rmax_bucket(int r) { return r <= 32 ? 32 : (r <= 64 ? 64 : 128); }
 
 template <typename T, int RMAX>
-static void launch_pass(Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass<T, RMAX>), dim3(tiles, count), dim3(kThreads), 0, s, nodes, prof);
-}
-template <typename T, int RMAX>
 static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
   hipLaunchKernelGGL((k_ctl<T, RMAX>), dim3(count), dim3(kThreads), 0, s, nodes, done, startup);
 }
 
 template <typename T>
 static void pass_any(int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s) {
-  if (rb == 32) launch_pass<T, 32>(nodes, count, tiles, prof, s);
-  else if (rb == 64) launch_pass<T, 64>(nodes, count, tiles, prof, s);
-  else launch_pass<T, 128>(nodes, count, tiles, prof, s);
+  pass_launch(std::is_same<T, double>::value, rb, nodes, count, tiles, prof, s);
 }
 
 // Event pair around a pass launch when the measurement counters are on.
