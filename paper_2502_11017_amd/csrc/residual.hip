@@ -26,65 +26,100 @@ __global__ __launch_bounds__(kThreads) void k_cu(const T* __restrict__ C, const 
   }
 }
 
-// One 64 x 64 tile of E per block; each thread owns a 4 x 4 sub-grid with
-// stride 16 (rows ty + 16a, columns tx + 16b) so that A is read coalesced.
+// One 128 x 128 tile of E per block on FP64 MFMA (v_mfma_f64_16x16x4f64).
+// Wavefront w computes the 64 x 64 quadrant (w >> 1, w & 1) as 4 x 4 blocks of
+// 16 x 16.  Operand lanes: lane l supplies Bm[row 16i + (l & 15)][k + (l >> 4)]
+// and R[k + (l >> 4)][col 16j + (l & 15)]; the accumulator holds
+// D[4v + (l >> 4)][l & 15] in element v.  Out-of-range rows, columns and k are
+// zero operands, so they contribute E = 0.
+// The block's rows of Bm and columns of R are staged in LDS, KC values of k at
+// a time (rows padded by one double, so that the fragment reads are free of
+// bank conflicts); the fragments then come from LDS.  The LDS footprint
+// (~67 KB) and register count allow two blocks per CU, so one block's MFMAs
+// cover the other's staging and its reads of A in the epilogue.
 // part[3*block] = {max|E|, sum E^2, sum A^2} of the tile.
-constexpr int kRT = 64, kKC = 32;
+constexpr int kRT = 128, kKC = 32;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct ResidLds {
+  double B[kRT][kKC + 1];   // Bm rows of the block, k chunk
+  double R[kKC][kRT + 1];   // R columns of the block, k chunk
+  double red[3][kThreads / 64];
+};
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_resid_f64(const T* __restrict__ A, int64_t m, int64_t n,
-                                                        int64_t lda, int r, const double* __restrict__ Bm,
-                                                        const T* __restrict__ R, double* part) {
-  __shared__ double sB[kRT][kKC + 1];
-  __shared__ double sR[kKC][kRT + 1];
-  __shared__ double red[3][kThreads / 64];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int64_t i0 = (int64_t)blockIdx.y * kRT, j0 = (int64_t)blockIdx.x * kRT;
-  double acc[4][4];
+__global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict__ A, int64_t m, int64_t n,
+                                                         int64_t lda, int r, const double* __restrict__ Bm,
+                                                         const T* __restrict__ R, double* part) {
+  __shared__ ResidLds L;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.y * kRT, c0 = (int64_t)blockIdx.x * kRT;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;  // quadrant inside the block
+  f64x4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < r; k0 += kKC) {
     const int kc = min(kKC, r - k0);
-    for (int idx = tid; idx < kRT * kKC; idx += kThreads) {
-      const int ii = idx / kKC, kk = idx % kKC;
-      const int64_t i = i0 + ii;
-      sB[ii][kk] = (i < m && kk < kc) ? Bm[i * r + k0 + kk] : 0.0;
-    }
-    for (int idx = tid; idx < kKC * kRT; idx += kThreads) {
-      const int kk = idx / kRT, jj = idx % kRT;
-      const int64_t j = j0 + jj;
-      sR[kk][jj] = (j < n && kk < kc) ? (double)R[(int64_t)(k0 + kk) * n + j] : 0.0;
+    // stage: thread t loads Bm[r0 + (t >> 1)][k0 + 16 (t & 1) + q] and
+    // R[k0 + (t >> 3)][c0 + 16 (t & 7) + q], q < 16, all loads first
+    {
+      const int br = tid >> 1, bk = 16 * (tid & 1);
+      const int64_t row = r0 + br;
+      double vb[16], vr[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        vb[q] = (row < m && bk + q < kc) ? Bm[row * r + k0 + bk + q] : 0.0;
+      const int rk = tid >> 3, rc = 16 * (tid & 7);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t col = c0 + rc + q;
+        vr[q] = (rk < kc && col < n) ? (double)R[(int64_t)(k0 + rk) * n + col] : 0.0;
+      }
+      __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll
+      for (int q = 0; q < 16; ++q) L.B[br][bk + q] = vb[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) L.R[rk][rc + q] = vr[q];
     }
     __syncthreads();
-    for (int kk = 0; kk < kc; ++kk) {
-      double bv[4], rv[4];
+    for (int k = 0; k < kc; k += 4) {
+      double af[4], bf[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) bv[a] = sB[ty + 16 * a][kk];
+      for (int i = 0; i < 4; ++i) af[i] = L.B[wr + 16 * i + lr][k + lk];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) rv[b] = sR[kk][tx + 16 * b];
+      for (int j = 0; j < 4; ++j) bf[j] = L.R[k + lk][wc + 16 * j + lr];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(bv[a], rv[b], acc[a][b]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
   double emax = 0.0, esq = 0.0, asq = 0.0;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t i = i0 + ty + 16 * a;
-    if (i >= m) continue;
+  for (int i = 0; i < 4; ++i) {
+    double pa[4][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t j = j0 + tx + 16 * b;
-      if (j >= n) continue;
-      const double av = (double)A[i * lda + j];
-      const double e = av - acc[a][b];
-      emax = fmax(emax, fabs(e));
-      esq = fma(e, e, esq);
-      asq = fma(av, av, asq);
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + wr + 16 * i + 4 * v + lk;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = c0 + wc + 16 * j + lr;
+        pa[j][v] = (row < m && col < n) ? (double)A[row * lda + col] : 0.0;
+      }
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double av = pa[j][v];
+        const double e = av - acc[i][j][v];
+        emax = fmax(emax, fabs(e));
+        esq = fma(e, e, esq);
+        asq = fma(av, av, asq);
+      }
   }
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
@@ -92,17 +127,17 @@ __global__ __launch_bounds__(kThreads) void k_resid_f64(const T* __restrict__ A,
     esq += __shfl_xor(esq, s, 64);
     asq += __shfl_xor(asq, s, 64);
   }
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = emax;
-    red[1][tid >> 6] = esq;
-    red[2][tid >> 6] = asq;
+  if (lane == 0) {
+    L.red[0][w] = emax;
+    L.red[1][w] = esq;
+    L.red[2][w] = asq;
   }
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < kThreads / 64; ++w) {
-      emax = fmax(emax, red[0][w]);
-      esq += red[1][w];
-      asq += red[2][w];
+    for (int q = 1; q < kThreads / 64; ++q) {
+      emax = fmax(emax, L.red[0][q]);
+      esq += L.red[1][q];
+      asq += L.red[2][q];
     }
     const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     part[3 * bid + 0] = emax;
@@ -161,7 +196,7 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
     set_error("matrix too tall for the residual grid");
     return CUR_ERR_ARG;
   }
-  hipLaunchKernelGGL((k_resid_f64<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
+  hipLaunchKernelGGL((k_resid_mfma<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
                      lda, r, Bm, R, part);
   hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kThreads), 0, s, part, nb, out);
   CUR_HIP_CHECK(hipGetLastError());
