@@ -134,6 +134,14 @@ cur_status ensure_arena(cur_ctx ctx, size_t bytes);
 // register bucket of r (32, 64 or 128), prof the device byte counter or null.
 void pass_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 
+// Reduced-precision residual (residual_mp.hip): scratch bytes, tile count, and
+// the launches that turn Bm (FP64, formed by the caller) into tile partials.
+size_t residual_mp_scratch(int64_t m, int64_t n, int r, int prec);
+int64_t residual_mp_tiles(int64_t m, int64_t n);
+cur_status residual_mp_launch(cur_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, int r,
+                              const double* Bm, const float* R, int prec, char* scratch, size_t scratch_bytes,
+                              double* part, int64_t* nb);
+
 cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                            int64_t lda, int r, const cur_opts& o, int64_t* I, int64_t* J,
                            cur_info* info);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "cur_device.hpp"
@@ -179,26 +180,38 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
                                 const T* C, const double* U, const T* R, int prec, double* cheb,
                                 double* fro_rel) {
   hipStream_t s = ctx->stream;
-  (void)prec;
+  const bool mp = prec != CUR_PREC_NATIVE;  // FP32 input only (checked by the API)
   const int64_t gx = (n + kRT - 1) / kRT, gy = (m + kRT - 1) / kRT;
-  const int64_t nb = gx * gy;
+  const int64_t nb = mp ? residual_mp_tiles(m, n) : gx * gy;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t bytes = al(sizeof(double) * m * r) + al(sizeof(double) * 3 * nb) + 256;
-  cur_status st = ensure_arena(ctx, bytes);
+  const size_t sbm = al(sizeof(double) * m * r), spart = al(sizeof(double) * 3 * nb);
+  const size_t smp = mp ? residual_mp_scratch(m, n, r, prec) : 0;
+  cur_status st = ensure_arena(ctx, sbm + spart + 256 + smp);
   if (st != CUR_OK) return st;
   char* base = (char*)ctx->arena;
   double* Bm = (double*)base;
-  double* part = (double*)(base + al(sizeof(double) * m * r));
-  double* out = (double*)(base + al(sizeof(double) * m * r) + al(sizeof(double) * 3 * nb));
+  double* part = (double*)(base + sbm);
+  double* out = (double*)(base + sbm + spart);
   const int g1 = (int)std::min<int64_t>((m * r + kThreads - 1) / kThreads, 16384);
   hipLaunchKernelGGL((k_cu<T>), dim3(std::max(g1, 1)), dim3(kThreads), 0, s, C, U, m, r, Bm);
-  if (gy > 65535) {
-    set_error("matrix too tall for the residual grid");
-    return CUR_ERR_ARG;
+  int64_t nparts = nb;
+  if (mp) {
+    if constexpr (std::is_same<T, float>::value) {
+      st = residual_mp_launch(ctx, A, m, n, lda, r, Bm, R, prec, base + sbm + spart + 256, smp, part, &nparts);
+      if (st != CUR_OK) return st;
+    } else {
+      set_error("reduced-precision residual needs FP32 input");
+      return CUR_ERR_ARG;
+    }
+  } else {
+    if (gy > 65535) {
+      set_error("matrix too tall for the residual grid");
+      return CUR_ERR_ARG;
+    }
+    hipLaunchKernelGGL((k_resid_mfma<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
+                       lda, r, Bm, R, part);
   }
-  hipLaunchKernelGGL((k_resid_mfma<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
-                     lda, r, Bm, R, part);
-  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kThreads), 0, s, part, nb, out);
+  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kThreads), 0, s, part, nparts, out);
   CUR_HIP_CHECK(hipGetLastError());
   double h[3];
   CUR_HIP_CHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
