@@ -57,6 +57,48 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def bench_e1(cur, W, torch, dev, reps=3):
+    """Residual of the tall FP32 workload (1,048,576 x 1024, rank-128 Gaussian
+    product + N(0, 1e-4) noise, r = 128) in the three precisions.  The FP32
+    selection and assembly run once (untimed here); each residual is timed
+    over `reps` calls.  The error of the BF16x3 and FP8 forms is taken against
+    the native form (FP64 arithmetic on the FP32 data), which agrees with the
+    FP64 oracle to 1e-10 ||A||_C (tests/test_gpu_mixed.py checks all three
+    forms against the oracle at a reduced height)."""
+    m, n, r = 1 << 20, 1024, 128
+    log(f"e1: generating the tall FP32 workload {m}x{n} on the GPU")
+    A = W.c4(seed=4, device=dev, m=m, n=n, k=128)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    res = cur.select(A, r)
+    torch.cuda.synchronize()
+    t_sel = time.perf_counter() - a
+    C, U, R = cur.assemble(A, res["I"], res["J"])
+    out = {"workload": f"{m}x{n} FP32, rank-128 Gaussian product + N(0,1e-4) noise, r={r}",
+           "select_ms": 1e3 * t_sel, "select_status": res["status"], "forms": {}}
+    ref = None
+    for name, prec in (("native_fp64_arith", cur.PREC_NATIVE), ("bf16x3", cur.PREC_BF16X3), ("fp8", cur.PREC_FP8)):
+        cur.residual(A, C, U, R, prec)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            cheb, fro = cur.residual(A, C, U, R, prec)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - a) / reps
+        if ref is None:
+            ref = (cheb, fro)
+        f = {"ms": 1e3 * t, "cheb": cheb, "fro_rel": fro,
+             "tflops": 2.0 * m * n * r / t / 1e12,
+             "a_stream_gbs": m * n * 4 / t / 1e9,
+             "cheb_rel_err_vs_native": abs(cheb - ref[0]) / ref[0],
+             "fro_rel_err_vs_native": abs(fro - ref[1]) / ref[1]}
+        out["forms"][name] = f
+        log(f"e1 {name}: {1e3 * t:.2f} ms, cheb {cheb:.6e}, fro {fro:.6e}")
+    del A, C, U, R
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +110,8 @@ def main():
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage breakdown")
     ap.add_argument("--host-matrix", action="store_true",
                     help="build the C2 matrix on the host and copy it over (for counter runs)")
+    ap.add_argument("--no-e1", action="store_true",
+                    help="skip the reduced-precision residual figures on the tall FP32 workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="one untimed device copy of this size, the calibration of the byte counters")
     args = ap.parse_args()
@@ -188,6 +232,10 @@ def main():
                 - orc.logvol(A32h, I, J)))
         del A32
 
+    e1 = None
+    if not args.no_e1:
+        e1 = bench_e1(cur, W, torch, dev)
+
     out = {
         "metric": "CUR selections/sec + swap-loop HBM GB/s at volume ratio >=0.99 vs FP64 oracle",
         "value": sel_per_s,
@@ -221,6 +269,7 @@ def main():
         "selection": {"status": res["status"], "swaps": res["swaps"], "phases": res["phases"],
                       "refreshes": res["refreshes"], "nodes": res["nodes"], "logvol": res["logvol"]},
         "f32": f32,
+        "e1_reduced_precision_residual": e1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -11,22 +11,6 @@
 
 namespace cur {
 
-// Bm = C U (m x r, FP64), sums over l ascending.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cu(const T* __restrict__ C, const double* __restrict__ U,
-                                                 int64_t m, int r, double* __restrict__ Bm) {
-  const int64_t total = m * r;
-  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kThreads) {
-    const int64_t i = idx / r;
-    const int k = (int)(idx - i * r);
-    const T* c = C + i * r;
-    double s = 0.0;
-    for (int l = 0; l < r; ++l) s = fma((double)c[l], U[l * r + k], s);
-    Bm[idx] = s;
-  }
-}
-
 // One 128 x 128 tile of E per block on FP64 MFMA (v_mfma_f64_16x16x4f64).
 // Wavefront w computes the 64 x 64 quadrant (w >> 1, w & 1) as 4 x 4 blocks of
 // 16 x 16.  Operand lanes: lane l supplies Bm[row 16i + (l & 15)][k + (l >> 4)]
@@ -147,6 +131,66 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
   }
 }
 
+// Bm = C U on FP64 MFMA, one 128-row x 128-column tile of Bm per block (r <= 128
+// columns, so one column tile), the same operand staging and lane layout as
+// k_resid_mfma with C as the row operand and U as the column operand.
+template <typename T>
+__global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C, const double* __restrict__ U,
+                                                         int64_t m, int r, double* __restrict__ Bm) {
+  __shared__ ResidLds L;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * kRT;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < r; k0 += kKC) {
+    const int kc = min(kKC, r - k0);
+    {
+      const int br = tid >> 1, bk = 16 * (tid & 1);
+      const int64_t row = r0 + br;
+      double vb[16], vr[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) vb[q] = (row < m && bk + q < kc) ? (double)C[row * r + k0 + bk + q] : 0.0;
+      const int rk = tid >> 3, rc = 16 * (tid & 7);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) vr[q] = (rk < kc && rc + q < r) ? U[(int64_t)(k0 + rk) * r + rc + q] : 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 16; ++q) L.B[br][bk + q] = vb[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) L.R[rk][rc + q] = vr[q];
+    }
+    __syncthreads();
+    for (int k = 0; k < kc; k += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = L.B[wr + 16 * i + lr][k + lk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = L.R[k + lk][wc + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + wr + 16 * i + 4 * v + lk;
+      if (row >= m) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = wc + 16 * j + lr;
+        if (col < r) Bm[row * r + col] = acc[i][j][v];
+      }
+    }
+}
+
 // Deterministic final reduction of the tile partials (fixed order).
 __global__ __launch_bounds__(kThreads) void k_resid_final(const double* part, int64_t nb, double* out) {
   double emax = 0.0, esq = 0.0, asq = 0.0;
@@ -192,8 +236,12 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   double* Bm = (double*)base;
   double* part = (double*)(base + sbm);
   double* out = (double*)(base + sbm + spart);
-  const int g1 = (int)std::min<int64_t>((m * r + kThreads - 1) / kThreads, 16384);
-  hipLaunchKernelGGL((k_cu<T>), dim3(std::max(g1, 1)), dim3(kThreads), 0, s, C, U, m, r, Bm);
+  const int64_t gm = (m + kRT - 1) / kRT;
+  if (gm > 0x7fffffff) {
+    set_error("matrix too tall for the residual grid");
+    return CUR_ERR_ARG;
+  }
+  hipLaunchKernelGGL((k_cu_mfma<T>), dim3((unsigned)gm), dim3(kThreads), 0, s, C, U, m, r, Bm);
   int64_t nparts = nb;
   if (mp) {
     if constexpr (std::is_same<T, float>::value) {

@@ -66,58 +66,79 @@ __device__ __forceinline__ uint8_t to_e4m3(float x) {
 }
 __device__ __forceinline__ float from_e4m3(uint8_t q) { return __builtin_amdgcn_cvt_f32_fp8((int)q, 0); }
 
-// One strip of length r (values x[k * stride]) -> scale s and two e4m3 terms
-// (q1, q2 at q[k], k < rp; zero padding).  One thread per strip.
+// One strip of length r <= 128 (values x[k * stride]) -> scale s and two e4m3
+// terms (q1, q2 at q[k], k < rp; zero padding).  One wavefront per strip:
+// lane l handles k = l and k = l + 64.
 template <typename V>
 __device__ void split_strip_fp8(const V* x, int64_t stride, int r, int rp, uint8_t* q1, uint8_t* q2, float* s) {
-  double amax = 0.0;
-  for (int k = 0; k < r; ++k) amax = fmax(amax, fabs((double)x[k * stride]));
+  const int lane = threadIdx.x & 63;
+  double v0 = lane < r ? (double)x[lane * stride] : 0.0;
+  double v1 = lane + 64 < r ? (double)x[(lane + 64) * stride] : 0.0;
+  double amax = fmax(fabs(v0), fabs(v1));
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) amax = fmax(amax, __shfl_xor(amax, sh, 64));
   const float sc = amax > 0.0 ? (float)(amax / 448.0) : 1.0f;
-  const float inv = 1.0f / sc;
-  for (int k = 0; k < rp; ++k) {
-    const float v = k < r ? (float)((double)x[k * stride] * (double)inv) : 0.0f;
+  const double inv = 1.0 / (double)sc;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + 64 * h;
+    if (k >= rp) break;
+    const float v = (float)((h ? v1 : v0) * inv);
     const uint8_t a = to_e4m3(v);
     q1[k] = a;
     q2[k] = to_e4m3(16.0f * (v - from_e4m3(a)));
   }
-  *s = sc;
+  if (lane == 0) *s = sc;
 }
 
 __global__ __launch_bounds__(kThreads) void k_split_rows_fp8(const double* __restrict__ Bm, int64_t m, int r, int rp,
                                                              uint8_t* q1, uint8_t* q2, float* s) {
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads)
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+  for (int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); i < m; i += waves)
     split_strip_fp8<double>(Bm + i * r, 1, r, rp, q1 + i * rp, q2 + i * rp, s + i);
 }
 
 __global__ __launch_bounds__(kThreads) void k_split_cols_fp8(const float* __restrict__ R, int r, int64_t n, int rp,
                                                              uint8_t* q1, uint8_t* q2, float* s) {
-  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads)
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+  for (int64_t j = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); j < n; j += waves)
     split_strip_fp8<float>(R + j, n, r, rp, q1 + j * rp, q2 + j * rp, s + j);
 }
 
 // ---------------------------------------------------------------- the tile kernel
 // Wavefront w computes the 64 x 64 quadrant (w >> 1, w & 1) of the block's
-// 128 x 128 tile as 4 x 4 MFMA blocks of 16 x 16.  Rows or columns beyond m, n
-// are zero operands and are skipped in the epilogue.
+// 128 x 128 tile as 4 x 4 MFMA blocks of 16 x 16.  The block's rows of the
+// split Bm and columns of the split R are staged in LDS, KC values of k at a
+// time (each row padded by 16 bytes); fragments are 16-byte (bf16) or 8-byte
+// (fp8) LDS reads.  ~70 KB of LDS, two blocks per CU, so one block's MFMAs
+// cover the other's staging and epilogue.  Rows or columns beyond m, n are
+// zero operands and are skipped in the epilogue.
 // part[3*block] = {max|E|, sum E^2, sum A^2}.
+constexpr int kMK = 64;  // k values per staged chunk
+
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_resid_mp(const float* __restrict__ A, int64_t m, int64_t n,
-                                                       int64_t lda, int rp, const void* __restrict__ a1v,
-                                                       const void* __restrict__ a2v, const float* __restrict__ as,
-                                                       const void* __restrict__ b1v, const void* __restrict__ b2v,
-                                                       const float* __restrict__ bs, double* part) {
-  __shared__ double red[3][kThreads / 64];
+struct MpLds {
+  static constexpr int ES = PREC == CUR_PREC_BF16X3 ? 2 : 1;  // bytes per element
+  static constexpr int ROWB = kMK * ES + 16;                  // bytes per staged row (padded)
+  alignas(16) uint8_t a[2][kMT * ROWB];                       // two terms of the row operand
+  alignas(16) uint8_t b[2][kMT * ROWB];                       // two terms of the column operand
+  double red[3][kThreads / 64];
+};
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads, 2) void k_resid_mp(const float* __restrict__ A, int64_t m, int64_t n,
+                                                          int64_t lda, int rp, const void* __restrict__ a1v,
+                                                          const void* __restrict__ a2v, const float* __restrict__ as,
+                                                          const void* __restrict__ b1v, const void* __restrict__ b2v,
+                                                          const float* __restrict__ bs, double* part) {
+  using L_t = MpLds<PREC>;
+  constexpr int ES = L_t::ES, ROWB = L_t::ROWB;
+  __shared__ L_t L;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.y * kMT + (w >> 1) * 64;
-  const int64_t c0 = (int64_t)blockIdx.x * kMT + (w & 1) * 64;
-  int64_t rowp[4], colp[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = r0 + 16 * i + lr, col = c0 + 16 * i + lr;
-    rowp[i] = (row < m ? row : m - 1) * rp + 8 * lk;  // clamped rows are masked in the epilogue
-    colp[i] = (col < n ? col : n - 1) * rp + 8 * lk;
-  }
+  const int64_t rb0 = (int64_t)blockIdx.y * kMT, cb0 = (int64_t)blockIdx.x * kMT;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const uint8_t* src[4] = {(const uint8_t*)a1v, (const uint8_t*)a2v, (const uint8_t*)b1v, (const uint8_t*)b2v};
   f32x4 acc[4][4], acc2[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -126,49 +147,70 @@ __global__ __launch_bounds__(kThreads) void k_resid_mp(const float* __restrict__
       acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
       acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int k0 = 0; k0 < rp; k0 += 32) {
-    if constexpr (PREC == CUR_PREC_BF16X3) {
-      const __bf16* ah = (const __bf16*)a1v;
-      const __bf16* al = (const __bf16*)a2v;
-      const __bf16* bh = (const __bf16*)b1v;
-      const __bf16* bl = (const __bf16*)b2v;
-      bf16x8 xh[4], xl[4], yh[4], yl[4];
+  for (int k0 = 0; k0 < rp; k0 += kMK) {
+    // stage: 4 operand terms x 128 strips x (kMK * ES) bytes as 16-byte pieces
+    constexpr int PIECES = kMK * ES / 16;  // per strip
+    constexpr int TOTAL = 4 * kMT * PIECES;
+    constexpr int PER = TOTAL / kThreads;
+    uint4 v[PER];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        xh[i] = *(const bf16x8*)(ah + rowp[i] + k0);
-        xl[i] = *(const bf16x8*)(al + rowp[i] + k0);
-        yh[i] = *(const bf16x8*)(bh + colp[i] + k0);
-        yl[i] = *(const bf16x8*)(bl + colp[i] + k0);
-      }
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * kThreads;
+      const int term = idx / (kMT * PIECES), rem = idx % (kMT * PIECES);
+      const int strip = rem / PIECES, piece = rem % PIECES;
+      const int64_t lim = term < 2 ? m : n;
+      const int64_t g = (term < 2 ? rb0 : cb0) + strip;
+      const int kk = k0 + piece * (16 / ES);
+      v[q] = (g < lim && kk < rp) ? *(const uint4*)(src[term] + (g * rp + kk) * ES) : make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();  // the previous chunk's fragments have been read
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * kThreads;
+      const int term = idx / (kMT * PIECES), rem = idx % (kMT * PIECES);
+      const int strip = rem / PIECES, piece = rem % PIECES;
+      uint8_t* dst = (term < 2 ? L.a[term] : L.b[term - 2]) + strip * ROWB + piece * 16;
+      *(uint4*)dst = v[q];
+    }
+    __syncthreads();
+    const int kc = min(kMK, rp - k0);
+    for (int k = 0; k < kc; k += 32) {
+      const int off = (k + 8 * lk) * ES;
+      if constexpr (PREC == CUR_PREC_BF16X3) {
+        bf16x8 xh[4], xl[4], yh[4], yl[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+          xh[i] = *(const bf16x8*)(L.a[0] + (wr + 16 * i + lr) * ROWB + off);
+          xl[i] = *(const bf16x8*)(L.a[1] + (wr + 16 * i + lr) * ROWB + off);
+          yh[i] = *(const bf16x8*)(L.b[0] + (wc + 16 * i + lr) * ROWB + off);
+          yl[i] = *(const bf16x8*)(L.b[1] + (wc + 16 * i + lr) * ROWB + off);
         }
-    } else {
-      const uint8_t* a1 = (const uint8_t*)a1v;
-      const uint8_t* a2 = (const uint8_t*)a2v;
-      const uint8_t* b1 = (const uint8_t*)b1v;
-      const uint8_t* b2 = (const uint8_t*)b2v;
-      long x1[4], x2[4], y1[4], y2[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        x1[i] = *(const long*)(a1 + rowp[i] + k0);
-        x2[i] = *(const long*)(a2 + rowp[i] + k0);
-        y1[i] = *(const long*)(b1 + colp[i] + k0);
-        y2[i] = *(const long*)(b2 + colp[i] + k0);
-      }
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+          }
+      } else {
+        long x1[4], x2[4], y1[4], y2[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x1[i], y1[j], acc[i][j], 0, 0, 0);
-          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x1[i], y2[j], acc2[i][j], 0, 0, 0);
-          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x2[i], y1[j], acc2[i][j], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+          x1[i] = *(const long*)(L.a[0] + (wr + 16 * i + lr) * ROWB + off);
+          x2[i] = *(const long*)(L.a[1] + (wr + 16 * i + lr) * ROWB + off);
+          y1[i] = *(const long*)(L.b[0] + (wc + 16 * i + lr) * ROWB + off);
+          y2[i] = *(const long*)(L.b[1] + (wc + 16 * i + lr) * ROWB + off);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x1[i], y1[j], acc[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x1[i], y2[j], acc2[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(x2[i], y1[j], acc2[i][j], 0, 0, 0);
+          }
+      }
     }
   }
   double emax = 0.0, esq = 0.0, asq = 0.0;
@@ -176,12 +218,12 @@ __global__ __launch_bounds__(kThreads) void k_resid_mp(const float* __restrict__
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t row = r0 + 16 * i + 4 * lk + v;
+      const int64_t row = rb0 + wr + 16 * i + 4 * lk + v;
       if (row >= m) continue;
       const float sa = (PREC == CUR_PREC_FP8) ? as[row] : 1.0f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t col = c0 + 16 * j + lr;
+        const int64_t col = cb0 + wc + 16 * j + lr;
         if (col >= n) continue;
         float p = acc[i][j][v];
         if constexpr (PREC == CUR_PREC_FP8) p = sa * bs[col] * (p + 0.0625f * acc2[i][j][v]);
@@ -199,16 +241,16 @@ __global__ __launch_bounds__(kThreads) void k_resid_mp(const float* __restrict__
     asq += __shfl_xor(asq, s, 64);
   }
   if (lane == 0) {
-    red[0][w] = emax;
-    red[1][w] = esq;
-    red[2][w] = asq;
+    L.red[0][w] = emax;
+    L.red[1][w] = esq;
+    L.red[2][w] = asq;
   }
   __syncthreads();
   if (tid == 0) {
     for (int q = 1; q < kThreads / 64; ++q) {
-      emax = fmax(emax, red[0][q]);
-      esq += red[1][q];
-      asq += red[2][q];
+      emax = fmax(emax, L.red[0][q]);
+      esq += L.red[1][q];
+      asq += L.red[2][q];
     }
     const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     part[3 * bid + 0] = emax;
@@ -254,9 +296,9 @@ cur_status residual_mp_launch(cur_ctx ctx, const float* A, int64_t m, int64_t n,
     hipLaunchKernelGGL((k_resid_mp<CUR_PREC_BF16X3>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m,
                        n, lda, rp, a1, a2, as, b1, b2, bs, part);
   } else {
-    hipLaunchKernelGGL(k_split_rows_fp8, dim3(grid(m)), dim3(kThreads), 0, s, Bm, m, r, rp, (uint8_t*)a1,
+    hipLaunchKernelGGL(k_split_rows_fp8, dim3(grid(64 * m)), dim3(kThreads), 0, s, Bm, m, r, rp, (uint8_t*)a1,
                        (uint8_t*)a2, as);
-    hipLaunchKernelGGL(k_split_cols_fp8, dim3(grid(n)), dim3(kThreads), 0, s, R, r, n, rp, (uint8_t*)b1,
+    hipLaunchKernelGGL(k_split_cols_fp8, dim3(grid(64 * n)), dim3(kThreads), 0, s, R, r, n, rp, (uint8_t*)b1,
                        (uint8_t*)b2, bs);
     hipLaunchKernelGGL((k_resid_mp<CUR_PREC_FP8>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
                        lda, rp, a1, a2, as, b1, b2, bs, part);
