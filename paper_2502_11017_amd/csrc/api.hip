@@ -259,16 +259,16 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
   }
   if (!ctx) return arg_error("ctx is NULL");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  std::vector<cur_opts> ro(count);
+  for (int32_t i = 0; i < count; ++i) resolve_opts(opts, (cur_dtype)items[i].dtype, items[i].r, items[i].n, &ro[i]);
+  std::vector<cur_status> st(count, CUR_OK);
+  cur_status rc = select_batched_dispatch(ctx, count, items, ro, st.data());
+  if (rc != CUR_OK) return rc;
   cur_status worst = CUR_OK;
   for (int32_t i = 0; i < count; ++i) {
-    const cur_item& it = items[i];
-    cur_opts o;
-    resolve_opts(opts, (cur_dtype)it.dtype, it.r, it.n, &o);
-    cur_status st = select_dispatch(ctx, (cur_dtype)it.dtype, it.A, it.m, it.n, it.lda, it.r, o, it.I, it.J,
-                                    nullptr);
-    if (per_item) per_item[i] = st;
-    if (st < 0 && (worst >= 0 || st < worst)) worst = st;
-    else if (worst == CUR_OK && st > 0) worst = st;
+    if (per_item) per_item[i] = st[i];
+    if (st[i] < 0 && (worst >= 0 || st[i] < worst)) worst = st[i];
+    else if (worst == CUR_OK && st[i] > 0) worst = st[i];
   }
   return worst;
 }

@@ -63,6 +63,9 @@ struct Node {
   int64_t* I;        // r: selected rows (current order)
   int32_t* Jp;       // r: selected candidate positions (current order)
   double* dbg;       // 4 x kDbgRing swap log (kind, index, slot, pivot) for diagnostics
+  const void* src;   // leaves: the matrix A this tree selects from (element T)
+  int64_t lda;       // leaves: its leading dimension
+  int64_t col0;      // leaves: first column of the block
   int64_t tclk[8];   // wall-clock ticks spent in controller steps (diagnostics):
                      // build, col phase, col fresh, col swaps, sort, whole ctl, LU, inverse
   // ---- dynamic state (device) ----
@@ -141,6 +144,11 @@ int64_t residual_mp_tiles(int64_t m, int64_t n);
 cur_status residual_mp_launch(cur_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, int r,
                               const double* Bm, const float* R, int prec, char* scratch, size_t scratch_bytes,
                               double* part, int64_t* nb);
+
+// Independent selections of several matrices, run together per dtype and
+// rank bucket; per_item receives every item's status.
+cur_status select_batched_dispatch(cur_ctx ctx, int32_t count, const cur_item* items,
+                                   const std::vector<cur_opts>& opts, cur_status* per_item);
 
 cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                            int64_t lda, int r, const cur_opts& o, int64_t* I, int64_t* J,

@@ -76,10 +76,10 @@ __global__ __launch_bounds__(kThreads) void k_amax(const T* __restrict__ A, int6
 }
 
 // ---------------------------------------------------------------- leaf set-up
-// panel(:, c) = A(:, c0 + c) for the leaf's block, transposed through LDS.
+// panel(:, c) = A(:, c0 + c) for each leaf's block (the leaf's own matrix),
+// transposed through LDS.  grid (row tiles, column tiles of 64, leaves).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes, const T* __restrict__ A,
-                                                           int64_t lda, const int64_t* col0) {
+__global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes) {
   Node& nd = nodes[blockIdx.z];
   const int64_t m = nd.m;
   const int nc = nd.nc;
@@ -87,7 +87,8 @@ __global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes, const T*
   const int cb = blockIdx.y * 64;
   if (r0 >= m || cb >= nc) return;
   __shared__ T tile[kTR][65];
-  const int64_t c0 = col0[blockIdx.z];
+  const T* A = (const T*)nd.src;
+  const int64_t lda = nd.lda, c0 = nd.col0;
   // read kTR rows x 64 columns, lanes along the row
   for (int idx = threadIdx.x; idx < kTR * 64; idx += kThreads) {
     const int rr = idx >> 6, cc = idx & 63;
@@ -104,10 +105,10 @@ __global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes, const T*
 }
 
 // Leaf candidate lists: Jc = c0 + [0, nc), identity layout map.
-__global__ void k_leaf_init(Node* nodes, const int64_t* col0) {
+__global__ void k_leaf_init(Node* nodes) {
   Node& nd = nodes[blockIdx.x];
   for (int c = threadIdx.x; c < nd.nc; c += blockDim.x) {
-    nd.Jc[c] = col0[blockIdx.x] + c;
+    nd.Jc[c] = nd.col0 + c;
     nd.colmap[c] = c;
   }
 }
@@ -1015,12 +1016,22 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
 }
 
 // Root -> caller's I, J (ascending original indices, -1 padded).
-__global__ void k_finalize(const Node* root, int64_t* I, int64_t* J) {
-  const Node& nd = *root;
+// Root outputs of every tree: block j writes tree j's (I, J), entries past the
+// rank it reached are -1.
+struct RootOut {
+  int32_t node;  // index of the root in the node table
+  int32_t pad;
+  int64_t* I;
+  int64_t* J;
+};
+
+__global__ void k_finalize(const Node* nodes, const RootOut* roots) {
+  const RootOut ro = roots[blockIdx.x];
+  const Node& nd = nodes[ro.node];
   for (int k = threadIdx.x; k < nd.r; k += blockDim.x) {
     const bool ok = k < nd.q;
-    I[k] = ok ? nd.I[k] : -1;
-    J[k] = ok ? nd.Jc[nd.Jp[k]] : -1;
+    ro.I[k] = ok ? nd.I[k] : -1;
+    ro.J[k] = ok ? nd.Jc[nd.Jp[k]] : -1;
   }
 }
 
@@ -1143,201 +1154,312 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
   return rc;
 }
 
-template <typename T>
-static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
-                              const cur_opts& o, int64_t* I, int64_t* J, cur_info* info) {
-  hipStream_t s = ctx->stream;
-  const int w = o.col_block;
-  const double tau = o.tau;
-  const int smax = o.max_swaps;
-  const int rb = rmax_bucket(r);
+// Diagnostics (CUR_DEBUG set): unfinished, failed or capped nodes with their
+// last swaps, and the controller clocks summed per level.
+static void debug_report(cur_ctx ctx, const std::vector<Node>& h, const std::vector<int>& lfirst,
+                         const std::vector<int>& lcount) {
+  for (size_t l = 0; l < lfirst.size(); ++l)
+    for (int k = 0; k < lcount[l]; ++k) {
+      const Node& nd = h[lfirst[l] + k];
+      if (!(nd.err || nd.st != ST_DONE || nd.nocap)) continue;
+      std::fprintf(stderr, "cur: node level %zu index %d kind %d st %d err %d phase %d swaps %d phases %d "
+                   "refreshes %d q %d nc %d nocap %d\n", l, k, nd.kind, nd.st, nd.err, nd.phase, nd.swaps,
+                   nd.phases, nd.refreshes, nd.q, nd.nc, nd.nocap);
+      std::vector<double> ring(4 * kDbgRing);
+      if (hipMemcpy(ring.data(), nd.dbg, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+        const int n0 = nd.swaps > kDbgRing ? nd.swaps - kDbgRing : 0;
+        for (int q = n0; q < nd.swaps; ++q) {
+          const double* e = &ring[4 * (q % kDbgRing)];
+          std::fprintf(stderr, "  swap %d kind %.3f index %.0f slot %.0f pivot %.17g\n", q, e[0], e[1], e[2], e[3]);
+        }
+      }
+    }
+  int wclk = 100000;  // ticks per ms of wall_clock64 (100 MHz)
+  (void)hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, ctx->device);  // kHz
+  for (size_t l = 0; l < lfirst.size(); ++l) {
+    double tsum[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tmax = 0;
+    for (int k = 0; k < lcount[l]; ++k) {
+      const Node& nd = h[lfirst[l] + k];
+      for (int q = 0; q < 8; ++q) tsum[q] += nd.tclk[q];
+      tmax = std::max(tmax, (double)nd.tclk[5]);
+    }
+    std::fprintf(stderr, "cur: level %zu nodes %d ctl ms (sum over nodes): build %.2f (lu %.2f inv %.2f) col %.2f "
+                 "colfresh %.2f colswaps %.2f sort %.2f all %.2f; slowest node %.2f\n", l, lcount[l],
+                 tsum[0] / wclk, tsum[6] / wclk, tsum[7] / wclk, tsum[1] / wclk, tsum[2] / wclk, tsum[3] / wclk,
+                 tsum[4] / wclk, tsum[5] / wclk, tmax / wclk);
+  }
+}
 
-  // ---- a0: scan
+// One selection tree: a matrix, its options and outputs, and the plan of its
+// tree (nodes per level and where they sit in the combined level tables).
+template <typename T>
+struct TreeJob {
+  const T* A;
+  int64_t m, n, lda;
+  int r;
+  cur_opts o;
+  int64_t* I;
+  int64_t* J;
+  cur_info* info;
+  cur_status status = CUR_OK;
+  bool active = true;
   double theta = 0.0;
+  int w = 0, b = 0, leafmax = 0, ntiles = 0;
+  std::vector<int> count;   // nodes per level of this tree
+  std::vector<int> off;     // offset of this tree's nodes in each combined level
+  std::vector<int> ncmax;   // candidate capacity per level
+};
+
+// Runs the trees of `jobs` (one dtype, one rank bucket) together: level l of
+// every tree forms one node table, and each pass / controller launch covers
+// all of them.  A single cur_select is the one-tree case.  Per-tree statuses
+// go to jobs[j].status; the return value reports device failures only.
+template <typename T>
+static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs, cur_trace* tr) {
+  hipStream_t s = ctx->stream;
+  const int nj = (int)jobs.size();
+
+  // ---- a0: scans (one launch per matrix, one synchronization)
   {
-    cur_status ast = ensure_arena(ctx, 4096);
+    cur_status ast = ensure_arena(ctx, 4096 + 16 * (size_t)nj);
     if (ast != CUR_OK) return ast;
     unsigned long long* d = (unsigned long long*)ctx->arena;
-    CUR_HIP_CHECK(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), s));
-    const int blocks = (int)std::min<int64_t>(4096, (m * n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((k_amax<T>), dim3(std::max(blocks, 1)), dim3(kThreads), 0, s, A, m, n, lda, d);
-    unsigned long long hv[2];
-    CUR_HIP_CHECK(hipMemcpyAsync(hv, d, sizeof(hv), hipMemcpyDeviceToHost, s));
+    CUR_HIP_CHECK(hipMemsetAsync(d, 0, 16 * (size_t)nj, s));
+    for (int j = 0; j < nj; ++j) {
+      const TreeJob<T>& jb = jobs[j];
+      const int blocks = (int)std::min<int64_t>(4096, (jb.m * jb.n + kThreads - 1) / kThreads);
+      hipLaunchKernelGGL((k_amax<T>), dim3(std::max(blocks, 1)), dim3(kThreads), 0, s, jb.A, jb.m, jb.n, jb.lda,
+                         d + 2 * j);
+    }
+    std::vector<unsigned long long> hv(2 * (size_t)nj);
+    CUR_HIP_CHECK(hipMemcpyAsync(hv.data(), d, 16 * (size_t)nj, hipMemcpyDeviceToHost, s));
     CUR_HIP_CHECK(hipStreamSynchronize(s));
-    if (hv[1]) {
-      set_error("A holds NaN or Inf");
-      return CUR_ERR_NONFINITE;
-    }
-    double amax;
-    std::memcpy(&amax, &hv[0], sizeof(double));
-    if (amax == 0.0) {
-      if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->logvol = -HUGE_VAL;
+    for (int j = 0; j < nj; ++j) {
+      TreeJob<T>& jb = jobs[j];
+      if (hv[2 * j + 1]) {
+        jb.status = CUR_ERR_NONFINITE;
+        jb.active = false;
+        set_error("A holds NaN or Inf");
+        continue;
       }
-      std::vector<int64_t> neg(r, -1);
-      CUR_HIP_CHECK(hipMemcpyAsync(I, neg.data(), r * sizeof(int64_t), hipMemcpyHostToDevice, s));
-      CUR_HIP_CHECK(hipMemcpyAsync(J, neg.data(), r * sizeof(int64_t), hipMemcpyHostToDevice, s));
-      CUR_HIP_CHECK(hipStreamSynchronize(s));
-      set_error("A is zero");
-      return CUR_ERR_RANK;
+      double amax;
+      std::memcpy(&amax, &hv[2 * j], sizeof(double));
+      if (amax == 0.0) {
+        if (jb.info) {
+          std::memset(jb.info, 0, sizeof(*jb.info));
+          jb.info->logvol = -HUGE_VAL;
+        }
+        std::vector<int64_t> neg(jb.r, -1);
+        CUR_HIP_CHECK(hipMemcpyAsync(jb.I, neg.data(), jb.r * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        CUR_HIP_CHECK(hipMemcpyAsync(jb.J, neg.data(), jb.r * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        CUR_HIP_CHECK(hipStreamSynchronize(s));
+        jb.status = CUR_ERR_RANK;
+        jb.active = false;
+        set_error("A is zero");
+        continue;
+      }
+      // FP64: max(m,n) 2^-52 ||A||_C, the oracle's threshold.  FP32 path: the
+      // rounding accumulated by r elimination steps in FP32, r 2^-23 ||A||_C.
+      jb.theta = sizeof(T) == 8 ? (double)std::max(jb.m, jb.n) * 0x1p-52 * amax : (double)jb.r * 0x1p-23 * amax;
     }
-    // FP64: max(m,n) 2^-52 ||A||_C, the oracle's threshold.  FP32 path: the
-    // rounding accumulated by r elimination steps in FP32, r 2^-23 ||A||_C.
-    theta = sizeof(T) == 8 ? (double)std::max(m, n) * 0x1p-52 * amax : (double)r * 0x1p-23 * amax;
   }
 
-  // ---- plan the tree
-  const int64_t b64 = std::max<int64_t>(1, n / w);
-  const int b = (int)b64;
-  std::vector<LevelPlan> levels;
+  // ---- plan the trees and the combined level tables
+  int nlev = 0;
+  for (TreeJob<T>& jb : jobs) {
+    if (!jb.active) continue;
+    jb.w = jb.o.col_block;
+    jb.b = (int)std::max<int64_t>(1, jb.n / jb.w);
+    jb.count.clear();
+    for (int c = jb.b;;) {
+      jb.count.push_back(c);
+      if (c <= 1) break;
+      c = (c + 1) / 2;
+    }
+    jb.ntiles = (int)((jb.m + kTileRows - 1) / kTileRows);
+    jb.leafmax = 0;
+    for (int k = 0; k < jb.b; ++k) {
+      const int64_t c0 = (int64_t)k * jb.w, c1 = (k == jb.b - 1) ? jb.n : (int64_t)(k + 1) * jb.w;
+      jb.leafmax = std::max<int>(jb.leafmax, (int)(c1 - c0));
+    }
+    jb.ncmax.assign(jb.count.size(), 2 * jb.r);
+    jb.ncmax[0] = jb.leafmax;
+    nlev = std::max<int>(nlev, (int)jb.count.size());
+  }
+  if (nlev == 0) return CUR_OK;  // every tree ended at the scan
+  std::vector<int> lcount(nlev, 0), lfirst(nlev, 0);
+  for (TreeJob<T>& jb : jobs) {
+    if (!jb.active) continue;
+    jb.off.assign(jb.count.size(), 0);
+    for (size_t l = 0; l < jb.count.size(); ++l) {
+      jb.off[l] = lcount[l];
+      lcount[l] += jb.count[l];
+    }
+  }
   int total = 0;
-  for (int c = b;;) {
-    levels.push_back({c, total});
-    total += c;
-    if (c <= 1) break;
-    c = (c + 1) / 2;
+  for (int l = 0; l < nlev; ++l) {
+    lfirst[l] = total;
+    total += lcount[l];
   }
-  const int ntiles = (int)((m + kTileRows - 1) / kTileRows);
-  // candidate capacity of each level
-  std::vector<int> ncmax(levels.size());
-  int leafmax = 0;
-  for (int k = 0; k < b; ++k) {
-    const int64_t c0 = (int64_t)k * w, c1 = (k == b - 1) ? n : (int64_t)(k + 1) * w;
-    leafmax = std::max<int>(leafmax, (int)(c1 - c0));
-  }
-  ncmax[0] = leafmax;
-  for (size_t l = 1; l < levels.size(); ++l) ncmax[l] = 2 * r;
 
   // ---- workspace layout
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  size_t bytes = 4096;  // scan words + done counters
-  bytes += al(sizeof(Node) * total);
-  for (size_t l = 0; l < levels.size(); ++l) {
-    const int nc = ncmax[l];
+  auto node_bytes = [&](const TreeJob<T>& jb, int l) {
+    const int nc = jb.ncmax[l], r = jb.r;
     const int wd = std::max(nc, r);
+    const int64_t m = jb.m;
     size_t per = 0;
-    per += al(sizeof(T) * m * nc);            // panel
-    per += al(sizeof(T) * m * wd);            // work
-    per += al(sizeof(double) * r * r);        // X
-    per += al(sizeof(double) * r * nc);       // Bc
+    per += al(sizeof(T) * m * nc);                // panel
+    per += al(sizeof(T) * m * wd);                // work
+    per += al(sizeof(double) * r * r);            // X
+    per += al(sizeof(double) * r * nc);           // Bc
     per += al(sizeof(double) * (wd + 128 + nc));  // vec (w | rowk)
-    per += al(sizeof(Partial) * ntiles);
-    per += al(sizeof(int64_t) * nc);          // Jc
-    per += al(sizeof(int32_t) * nc) * 2;      // colmap, srcpos
-    per += al(nc);                            // insel
+    per += al(sizeof(Partial) * jb.ntiles);
+    per += al(sizeof(int64_t) * nc);              // Jc
+    per += al(sizeof(int32_t) * nc) * 2;          // colmap, srcpos
+    per += al(nc);                                // insel
     per += al(sizeof(int64_t) * r) + al(sizeof(int32_t) * r);
     per += al(sizeof(double) * 4 * kDbgRing);
-    bytes += per * levels[l].count;
+    return per;
+  };
+  size_t bytes = 4096;  // done counters (16 per level)
+  bytes += al(sizeof(Node) * total);
+  bytes += al(sizeof(RootOut) * nj);
+  for (const TreeJob<T>& jb : jobs)
+    if (jb.active)
+      for (size_t l = 0; l < jb.count.size(); ++l) bytes += node_bytes(jb, (int)l) * jb.count[l];
+  const int rtr = tr ? jobs[0].r : 0;
+  if (tr) bytes += al(sizeof(int64_t) * 2 * (size_t)total * rtr);  // export buffers
+  if (16 * nlev * (int)sizeof(int32_t) > 4096) {
+    set_error("tree too deep");
+    return CUR_ERR_INTERNAL;
   }
-  bytes += al(sizeof(int64_t) * b);  // leaf col0
-  bytes += al(sizeof(int64_t) * 2 * (size_t)total * r);  // export buffers
   cur_status st = ensure_arena(ctx, bytes);
   if (st != CUR_OK) return st;
   Arena ar{(char*)ctx->arena, ctx->arena_bytes, 0};
   int32_t* d_done = (int32_t*)ar.take(4096);
   Node* d_nodes = (Node*)ar.take(sizeof(Node) * total);
+  RootOut* d_roots = (RootOut*)ar.take(sizeof(RootOut) * nj);
   std::vector<Node> h(total);
   std::memset(h.data(), 0, sizeof(Node) * total);
-  for (size_t l = 0; l < levels.size(); ++l) {
-    const int nc = ncmax[l];
-    const int wd = std::max(nc, r);
-    for (int k = 0; k < levels[l].count; ++k) {
-      Node& nd = h[levels[l].first + k];
-      nd.m = m;
-      nd.r = r;
-      nd.ncmax = nc;
-      nd.ntiles = ntiles;
-      nd.smax = smax;
-      nd.tau = tau;
-      nd.theta = theta;
-      nd.panel = ar.take(sizeof(T) * m * nc);
-      nd.work = ar.take(sizeof(T) * m * wd);
-      nd.X = (double*)ar.take(sizeof(double) * r * r);
-      nd.Bc = (double*)ar.take(sizeof(double) * r * nc);
-      nd.vec = (double*)ar.take(sizeof(double) * (wd + 128 + nc));
-      nd.part = (Partial*)ar.take(sizeof(Partial) * ntiles);
-      nd.Jc = (int64_t*)ar.take(sizeof(int64_t) * nc);
-      nd.colmap = (int32_t*)ar.take(sizeof(int32_t) * nc);
-      nd.srcpos = (int32_t*)ar.take(sizeof(int32_t) * nc);
-      nd.insel = (uint8_t*)ar.take(nc);
-      nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
-      nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
-      nd.dbg = (double*)ar.take(sizeof(double) * 4 * kDbgRing);
-      if (!nd.panel || !nd.work || !nd.insel || !nd.Jp) {
-        set_error("workspace layout overflow");
-        return CUR_ERR_INTERNAL;
-      }
-      if (l == 0) {
-        const int64_t c0 = (int64_t)k * w, c1 = (k == b - 1) ? n : (int64_t)(k + 1) * w;
-        nd.kind = KIND_LEAF;
-        nd.child0 = nd.child1 = -1;
-        nd.nc = (int)(c1 - c0);
-        nd.st = ST_ACA;
-        nd.t = 0;
-        nd.na = nd.nc;
-        nd.steps = (int)std::min<int64_t>(std::min<int64_t>(r, nd.nc), m);
-      } else {
-        const int pc = levels[l - 1].count;
-        if (2 * k + 1 < pc) {
-          nd.kind = KIND_MERGE;
-          nd.child0 = 2 * k;
-          nd.child1 = 2 * k + 1;
-        } else {
-          nd.kind = KIND_PROMOTED;
-          nd.child0 = 2 * k;
-          nd.child1 = -1;
-          const Node& c = h[levels[l - 1].first + 2 * k];
-          nd.panel = c.panel;
-          nd.Jc = c.Jc;
-          nd.ncmax = c.ncmax;
+  int maxm = 0, rmax = 0, leafmax = 0, maxtiles = 0;
+  int64_t iter_bound = 0;
+  std::vector<RootOut> roots;
+  for (TreeJob<T>& jb : jobs) {
+    if (!jb.active) continue;
+    const int r = jb.r;
+    maxm = std::max<int>(maxm, (int)std::min<int64_t>(jb.m, INT32_MAX));
+    rmax = std::max(rmax, r);
+    leafmax = std::max(leafmax, jb.leafmax);
+    maxtiles = std::max(maxtiles, jb.ntiles);
+    iter_bound = std::max<int64_t>(iter_bound, 16 * (int64_t)(r + 4) + 8 * (int64_t)jb.o.max_swaps + 4096);
+    for (size_t l = 0; l < jb.count.size(); ++l) {
+      const int nc = jb.ncmax[l];
+      const int wd = std::max(nc, r);
+      for (int k = 0; k < jb.count[l]; ++k) {
+        Node& nd = h[lfirst[l] + jb.off[l] + k];
+        nd.m = jb.m;
+        nd.r = r;
+        nd.ncmax = nc;
+        nd.ntiles = jb.ntiles;
+        nd.smax = jb.o.max_swaps;
+        nd.tau = jb.o.tau;
+        nd.theta = jb.theta;
+        nd.panel = ar.take(sizeof(T) * jb.m * nc);
+        nd.work = ar.take(sizeof(T) * jb.m * wd);
+        nd.X = (double*)ar.take(sizeof(double) * r * r);
+        nd.Bc = (double*)ar.take(sizeof(double) * r * nc);
+        nd.vec = (double*)ar.take(sizeof(double) * (wd + 128 + nc));
+        nd.part = (Partial*)ar.take(sizeof(Partial) * jb.ntiles);
+        nd.Jc = (int64_t*)ar.take(sizeof(int64_t) * nc);
+        nd.colmap = (int32_t*)ar.take(sizeof(int32_t) * nc);
+        nd.srcpos = (int32_t*)ar.take(sizeof(int32_t) * nc);
+        nd.insel = (uint8_t*)ar.take(nc);
+        nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
+        nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
+        nd.dbg = (double*)ar.take(sizeof(double) * 4 * kDbgRing);
+        if (!nd.panel || !nd.work || !nd.insel || !nd.Jp || !nd.dbg) {
+          set_error("workspace layout overflow");
+          return CUR_ERR_INTERNAL;
         }
-        nd.st = ST_DONE;
+        if (l == 0) {
+          const int64_t c0 = (int64_t)k * jb.w, c1 = (k == jb.b - 1) ? jb.n : (int64_t)(k + 1) * jb.w;
+          nd.kind = KIND_LEAF;
+          nd.child0 = nd.child1 = -1;
+          nd.nc = (int)(c1 - c0);
+          nd.st = ST_ACA;
+          nd.t = 0;
+          nd.na = nd.nc;
+          nd.steps = (int)std::min<int64_t>(std::min<int64_t>(r, nd.nc), jb.m);
+          nd.src = jb.A;
+          nd.lda = jb.lda;
+          nd.col0 = c0;
+        } else {
+          const int pc = jb.count[l - 1], po = jb.off[l - 1];
+          if (2 * k + 1 < pc) {
+            nd.kind = KIND_MERGE;
+            nd.child0 = po + 2 * k;
+            nd.child1 = po + 2 * k + 1;
+          } else {
+            nd.kind = KIND_PROMOTED;
+            nd.child0 = po + 2 * k;
+            nd.child1 = -1;
+            const Node& c = h[lfirst[l - 1] + po + 2 * k];
+            nd.panel = c.panel;
+            nd.Jc = c.Jc;
+            nd.ncmax = c.ncmax;
+          }
+          nd.st = ST_DONE;
+        }
       }
     }
+    const int lt = (int)jb.count.size() - 1;
+    roots.push_back({lfirst[lt] + jb.off[lt], 0, jb.I, jb.J});
   }
-  int64_t* d_col0 = (int64_t*)ar.take(sizeof(int64_t) * b);
-  int64_t* d_expI = (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * r);
-  int64_t* d_expJ = (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * r);
-  std::vector<int64_t> col0(b);
-  for (int k = 0; k < b; ++k) col0[k] = (int64_t)k * w;
-  CUR_HIP_CHECK(hipMemcpyAsync(d_col0, col0.data(), sizeof(int64_t) * b, hipMemcpyHostToDevice, s));
+  int64_t* d_expI = tr ? (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * rtr) : nullptr;
+  int64_t* d_expJ = tr ? (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * rtr) : nullptr;
   CUR_HIP_CHECK(hipMemcpyAsync(d_nodes, h.data(), sizeof(Node) * total, hipMemcpyHostToDevice, s));
+  CUR_HIP_CHECK(hipMemcpyAsync(d_roots, roots.data(), sizeof(RootOut) * roots.size(), hipMemcpyHostToDevice, s));
   CUR_HIP_CHECK(hipMemsetAsync(d_done, 0, 4096, s));
 
-  // ---- level 0
-  Node* L0 = d_nodes;
-  hipLaunchKernelGGL(k_leaf_init, dim3(b), dim3(kThreads), 0, s, L0, d_col0);
-  hipLaunchKernelGGL((k_panel_from_A<T>), dim3((m + kTR - 1) / kTR, (leafmax + 63) / 64, b),
-                     dim3(kThreads), 0, s, L0, A, lda, d_col0);
-  const int64_t iter_bound = 16 * (int64_t)(r + 4) + 8 * (int64_t)smax + 4096;
+  // ---- level 0: every leaf of every tree
   size_t prof_used = 0;
-  cur_status rc = run_level<T>(ctx, rb, L0, b, ntiles, d_done + 0, iter_bound, prof_used);
-  if (rc != CUR_OK) return rc;
+  {
+    const int b = lcount[0];
+    hipLaunchKernelGGL(k_leaf_init, dim3(b), dim3(kThreads), 0, s, d_nodes);
+    hipLaunchKernelGGL((k_panel_from_A<T>), dim3((maxm + kTR - 1) / kTR, (leafmax + 63) / 64, b), dim3(kThreads),
+                       0, s, d_nodes);
+    cur_status rc = run_level<T>(ctx, rb, d_nodes, b, maxtiles, d_done + 0, iter_bound, prof_used);
+    if (rc != CUR_OK) return rc;
+  }
 
   // ---- merges
-  for (size_t l = 1; l < levels.size(); ++l) {
-    Node* cur = d_nodes + levels[l].first;
-    Node* prev = d_nodes + levels[l - 1].first;
-    const int cnt = levels[l].count;
-    int32_t* dd = d_done + 16 * (int)l;
+  for (int l = 1; l < nlev; ++l) {
+    Node* cur = d_nodes + lfirst[l];
+    Node* prev = d_nodes + lfirst[l - 1];
+    const int cnt = lcount[l];
+    int lm = 0, lt = 0;
+    for (const TreeJob<T>& jb : jobs)
+      if (jb.active && (int)jb.count.size() > l) {
+        lm = std::max<int>(lm, (int)std::min<int64_t>(jb.m, INT32_MAX));
+        lt = std::max(lt, jb.ntiles);
+      }
+    int32_t* dd = d_done + 16 * l;
     hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev, dd);
-    const int gx = (int)std::min<int64_t>((m + kThreads - 1) / kThreads, 64);
-    hipLaunchKernelGGL((k_panel_build<T>), dim3(gx, 2 * r, cnt), dim3(kThreads), 0, s, cur, prev);
-    rc = run_level<T>(ctx, rb, cur, cnt, ntiles, dd, iter_bound, prof_used);
+    const int gx = (int)std::min<int64_t>((lm + kThreads - 1) / kThreads, 64);
+    hipLaunchKernelGGL((k_panel_build<T>), dim3(gx, 2 * rmax, cnt), dim3(kThreads), 0, s, cur, prev);
+    cur_status rc = run_level<T>(ctx, rb, cur, cnt, lt, dd, iter_bound, prof_used);
     if (rc != CUR_OK) return rc;
   }
 
   // ---- outputs
-  const Node* d_root = d_nodes + levels.back().first;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, d_root, I, J);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)roots.size()), dim3(kThreads), 0, s, d_nodes, d_roots);
   CUR_HIP_CHECK(hipMemcpyAsync(h.data(), d_nodes, sizeof(Node) * total, hipMemcpyDeviceToHost, s));
-  cur_trace* tr = o.trace;
   std::vector<int64_t> eI, eJ;
   if (tr) {
-    hipLaunchKernelGGL(k_export, dim3(total), dim3(kThreads), 0, s, d_nodes, d_expI, d_expJ, r);
-    eI.resize((size_t)total * r);
-    eJ.resize((size_t)total * r);
+    hipLaunchKernelGGL(k_export, dim3(total), dim3(kThreads), 0, s, d_nodes, d_expI, d_expJ, rtr);
+    eI.resize((size_t)total * rtr);
+    eJ.resize((size_t)total * rtr);
     CUR_HIP_CHECK(hipMemcpyAsync(eI.data(), d_expI, sizeof(int64_t) * eI.size(), hipMemcpyDeviceToHost, s));
     CUR_HIP_CHECK(hipMemcpyAsync(eJ.data(), d_expJ, sizeof(int64_t) * eJ.size(), hipMemcpyDeviceToHost, s));
   }
@@ -1352,88 +1474,62 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
       }
     }
   }
-
-  if (std::getenv("CUR_DEBUG")) {
-    for (size_t l = 0; l < levels.size(); ++l)
-      for (int k = 0; k < levels[l].count; ++k) {
-        const Node& nd = h[levels[l].first + k];
-        if (nd.err || nd.st != ST_DONE || nd.nocap) {
-          std::fprintf(stderr, "cur: node level %zu index %d kind %d st %d err %d phase %d swaps %d "
-                       "phases %d refreshes %d q %d nc %d nocap %d\n", l, k, nd.kind, nd.st, nd.err, nd.phase,
-                       nd.swaps, nd.phases, nd.refreshes, nd.q, nd.nc, nd.nocap);
-          std::vector<double> ring(4 * kDbgRing);
-          if (hipMemcpy(ring.data(), nd.dbg, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess) {
-            const int n0 = nd.swaps > kDbgRing ? nd.swaps - kDbgRing : 0;
-            for (int q = n0; q < nd.swaps; ++q) {
-              const double* e = &ring[4 * (q % kDbgRing)];
-              std::fprintf(stderr, "  swap %d kind %.3f index %.0f slot %.0f pivot %.17g\n", q, e[0], e[1], e[2], e[3]);
-            }
-          }
-        }
-      }
-  }
-  if (std::getenv("CUR_DEBUG")) {
-    int wclk = 100000;  // ticks per ms of wall_clock64 (100 MHz)
-    hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, ctx->device);  // kHz
-    for (size_t l = 0; l < levels.size(); ++l) {
-      double tsum[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tmax = 0;
-      for (int k = 0; k < levels[l].count; ++k) {
-        const Node& nd = h[levels[l].first + k];
-        for (int q = 0; q < 8; ++q) tsum[q] += nd.tclk[q];
-        tmax = std::max(tmax, (double)nd.tclk[5]);
-      }
-      std::fprintf(stderr, "cur: level %zu nodes %d ctl ms (sum over nodes): build %.2f (lu %.2f inv %.2f) col %.2f "
-                   "colfresh %.2f colswaps %.2f sort %.2f all %.2f; slowest node %.2f\n", l, levels[l].count,
-                   tsum[0] / wclk, tsum[6] / wclk, tsum[7] / wclk, tsum[1] / wclk, tsum[2] / wclk, tsum[3] / wclk,
-                   tsum[4] / wclk, tsum[5] / wclk, tmax / wclk);
-    }
-  }
-  cur_status result = CUR_OK;
+  if (std::getenv("CUR_DEBUG")) debug_report(ctx, h, lfirst, lcount);
   for (int k = 0; k < total; ++k)
     if (h[k].st != ST_DONE) {
       set_error("a tree node was left unfinished");
       return CUR_ERR_INTERNAL;
     }
-  int32_t nodes = 0, phases = 0, refreshes = 0;
-  int64_t swaps = 0;
-  bool nocap = false;
-  for (size_t l = 0; l < levels.size(); ++l)
-    for (int k = 0; k < levels[l].count; ++k) {
-      const Node& nd = h[levels[l].first + k];
-      if (nd.err) result = CUR_ERR_INTERNAL;
-      if (nd.kind == KIND_PROMOTED) continue;
-      nodes++;
-      phases += nd.phases;
-      refreshes += nd.refreshes;
-      swaps += nd.swaps;
-      nocap |= nd.nocap != 0;
+
+  // ---- per-tree results
+  for (TreeJob<T>& jb : jobs) {
+    if (!jb.active) continue;
+    auto node = [&](size_t l, int k) -> const Node& { return h[lfirst[l] + jb.off[l] + k]; };
+    cur_status result = CUR_OK;
+    int32_t nodes = 0, phases = 0, refreshes = 0;
+    int64_t swaps = 0;
+    bool nocap = false;
+    for (size_t l = 0; l < jb.count.size(); ++l)
+      for (int k = 0; k < jb.count[l]; ++k) {
+        const Node& nd = node(l, k);
+        if (nd.err) result = CUR_ERR_INTERNAL;
+        if (nd.kind == KIND_PROMOTED) continue;
+        nodes++;
+        phases += nd.phases;
+        refreshes += nd.refreshes;
+        swaps += nd.swaps;
+        nocap |= nd.nocap != 0;
+      }
+    const Node& root = node(jb.count.size() - 1, 0);
+    if (result == CUR_OK) {
+      if (root.is_short) {
+        result = CUR_ERR_RANK;
+        set_error("rank-short: fewer than r pivots above the threshold");
+      } else if (nocap) {
+        result = CUR_WARN_NOCONV;
+      }
+    } else {
+      set_error("singular cross met inside the swap loop");
     }
-  const Node& root = h[levels.back().first];
-  if (result == CUR_OK) {
-    if (root.is_short) {
-      result = CUR_ERR_RANK;
-      set_error("rank-short: fewer than r pivots above the threshold");
-    } else if (nocap) {
-      result = CUR_WARN_NOCONV;
+    if (jb.info) {
+      jb.info->rank = root.q;
+      jb.info->nodes = nodes;
+      jb.info->phases = phases;
+      jb.info->refreshes = refreshes;
+      jb.info->swaps = swaps;
+      jb.info->logvol = root.is_short ? -HUGE_VAL : std::log(root.vol_m) + root.vol_e * 0.69314718055994530942;
     }
-  } else {
-    set_error("singular cross met inside the swap loop");
+    jb.status = result;
   }
-  if (info) {
-    info->rank = root.q;
-    info->nodes = nodes;
-    info->phases = phases;
-    info->refreshes = refreshes;
-    info->swaps = swaps;
-    info->logvol = root.is_short ? -HUGE_VAL : std::log(root.vol_m) + root.vol_e * 0.69314718055994530942;
-  }
-  if (tr) {
+  if (tr && jobs[0].active) {
+    const TreeJob<T>& jb = jobs[0];
     const int cap = tr->capacity;
     int slot = 0;
-    for (size_t l = 0; l < levels.size(); ++l)
-      for (int k = 0; k < levels[l].count; ++k, ++slot) {
+    for (size_t l = 0; l < jb.count.size(); ++l)
+      for (int k = 0; k < jb.count[l]; ++k, ++slot) {
         if (slot >= cap) continue;
-        const Node& nd = h[levels[l].first + k];
+        const size_t gi = lfirst[l] + jb.off[l] + k;
+        const Node& nd = h[gi];
         int64_t* mt = tr->meta + (size_t)slot * kMetaFields;
         const bool pr = nd.kind == KIND_PROMOTED;
         mt[0] = (int64_t)l;
@@ -1447,22 +1543,79 @@ static cur_status select_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
         mt[8] = pr ? 0 : nd.refreshes;
         mt[9] = nd.is_short ? 0 : nd.vol_e;
         tr->vol_mant[slot] = nd.is_short ? 0.0 : nd.vol_m;
-        for (int j = 0; j < r; ++j) {
-          tr->I[(size_t)slot * r + j] = eI[(size_t)(levels[l].first + k) * r + j];
-          tr->J[(size_t)slot * r + j] = eJ[(size_t)(levels[l].first + k) * r + j];
+        for (int j = 0; j < rtr; ++j) {
+          tr->I[(size_t)slot * rtr + j] = eI[gi * rtr + j];
+          tr->J[(size_t)slot * rtr + j] = eJ[gi * rtr + j];
         }
       }
     tr->count = total;
   }
-  return result;
+  return CUR_OK;
+}
+
+template <typename T>
+static cur_status select_one(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r, const cur_opts& o,
+                             int64_t* I, int64_t* J, cur_info* info) {
+  std::vector<TreeJob<T>> jobs(1);
+  TreeJob<T>& jb = jobs[0];
+  jb.A = A;
+  jb.m = m;
+  jb.n = n;
+  jb.lda = lda;
+  jb.r = r;
+  jb.o = o;
+  jb.I = I;
+  jb.J = J;
+  jb.info = info;
+  cur_status rc = select_many<T>(ctx, rmax_bucket(r), jobs, o.trace);
+  if (rc != CUR_OK) return rc;
+  return jobs[0].status;
 }
 
 cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                            int64_t lda, int r, const cur_opts& o, int64_t* I, int64_t* J,
                            cur_info* info) {
   if (dtype == CUR_F64)
-    return select_impl<double>(ctx, (const double*)A, m, n, lda, r, o, I, J, info);
-  return select_impl<float>(ctx, (const float*)A, m, n, lda, r, o, I, J, info);
+    return select_one<double>(ctx, (const double*)A, m, n, lda, r, o, I, J, info);
+  return select_one<float>(ctx, (const float*)A, m, n, lda, r, o, I, J, info);
+}
+
+// Items of one dtype and one rank bucket run as one set of trees.
+template <typename T>
+static cur_status select_group(cur_ctx ctx, int rb, const std::vector<int>& idx, const cur_item* items,
+                               const std::vector<cur_opts>& opts, cur_status* per_item) {
+  std::vector<TreeJob<T>> jobs(idx.size());
+  for (size_t q = 0; q < idx.size(); ++q) {
+    const cur_item& it = items[idx[q]];
+    TreeJob<T>& jb = jobs[q];
+    jb.A = (const T*)it.A;
+    jb.m = it.m;
+    jb.n = it.n;
+    jb.lda = it.lda;
+    jb.r = it.r;
+    jb.o = opts[idx[q]];
+    jb.I = it.I;
+    jb.J = it.J;
+    jb.info = nullptr;
+  }
+  cur_status rc = select_many<T>(ctx, rb, jobs, nullptr);
+  for (size_t q = 0; q < idx.size(); ++q) per_item[idx[q]] = rc != CUR_OK ? rc : jobs[q].status;
+  return rc;
+}
+
+cur_status select_batched_dispatch(cur_ctx ctx, int32_t count, const cur_item* items, const std::vector<cur_opts>& opts,
+                                   cur_status* per_item) {
+  for (int f64 = 1; f64 >= 0; --f64)
+    for (int rb : {32, 64, 128}) {
+      std::vector<int> idx;
+      for (int32_t i = 0; i < count; ++i)
+        if ((items[i].dtype == CUR_F64) == (f64 == 1) && rmax_bucket(items[i].r) == rb) idx.push_back(i);
+      if (idx.empty()) continue;
+      cur_status rc = f64 ? select_group<double>(ctx, rb, idx, items, opts, per_item)
+                          : select_group<float>(ctx, rb, idx, items, opts, per_item);
+      if (rc != CUR_OK) return rc;
+    }
+  return CUR_OK;
 }
 
 }  // namespace cur

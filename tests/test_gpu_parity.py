@@ -233,3 +233,33 @@ def test_select_batched_matches_single(orc):
         assert st == o["status"]
         np.testing.assert_array_equal(I.cpu().numpy(), o["I"])
         np.testing.assert_array_equal(J.cpu().numpy(), o["J"])
+
+
+def test_select_batched_mixed_trees_match_single(orc):
+    """Trees of different depths, ranks (all three register buckets), dtypes,
+    and an all-zero item, run as one batch: every item equals its own
+    single-matrix selection bit for bit, and the FP64 items equal the oracle."""
+    say("case batched mixed")
+    specs = [(600, 512, 8, 11, torch.float64), (257, 96, 16, 12, torch.float64), (1500, 1024, 33, 13, torch.float64),
+             (800, 700, 64, 14, torch.float64), (900, 300, 100, 15, torch.float64), (1200, 640, 16, 16, torch.float32),
+             (333, 777, 64, 17, torch.float32), (400, 256, 8, 0, torch.float64)]
+    As, rs = [], []
+    for m, n, r, seed, dt in specs:
+        A = torch.zeros(m, n, dtype=dt, device=DEV) if seed == 0 else \
+            torch.from_numpy(W.gaussian(m, n, seed)).to(DEV).to(dt)
+        As.append(A)
+        rs.append(r)
+    outs, rc = cur.select_batched(As, rs)
+    for (I, J, st), A, r, (m, n, _, seed, dt) in zip(outs, As, rs, specs):
+        say(f"  item m={m} n={n} r={r} seed={seed} {dt} status {st}")
+        g = cur.select(A, r, allow=(cur.OK, cur.WARN_NOCONV, cur.ERR_RANK))
+        assert st == g["status"]
+        np.testing.assert_array_equal(I.cpu().numpy(), g["I"].cpu().numpy())
+        np.testing.assert_array_equal(J.cpu().numpy(), g["J"].cpu().numpy())
+        if dt == torch.float64 and seed != 0:
+            o = orc.select(A.cpu().numpy(), r)
+            assert st == o["status"]
+            np.testing.assert_array_equal(I.cpu().numpy(), o["I"])
+            np.testing.assert_array_equal(J.cpu().numpy(), o["J"])
+        if seed == 0:
+            assert st == cur.ERR_RANK
