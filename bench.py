@@ -99,6 +99,43 @@ def bench_e1(cur, W, torch, dev, reps=3):
     return out
 
 
+def bench_e2(cur, W, torch, dev, reps=2):
+    """The batched uneven form: 256 independent FP32 matrices, m and n uniform
+    in [256, 4096], r in {8, 16, 32, 64}, geometric spectra with ratio uniform
+    in [0.8, 0.95] (seeded).  All trees in one batched call, against the same
+    matrices selected one call at a time; the per-item index sets of the two
+    must agree."""
+    specs = W.c3_specs()
+    log(f"e2: generating {len(specs)} FP32 matrices")
+    As = [W.c3_matrix(sp, device=dev, dtype=torch.float32) for sp in specs]
+    rs = [sp[2] for sp in specs]
+    torch.cuda.synchronize()
+    cur.select_batched(As, rs)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        outs, rc = cur.select_batched(As, rs)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - a) / reps
+    a = time.perf_counter()
+    singles = [cur.select(A, r) for A, r in zip(As, rs)]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - a
+    same = sum(int(torch.equal(I, g["I"]) and torch.equal(J, g["J"]) and st == g["status"])
+               for (I, J, st), g in zip(outs, singles))
+    short = sum(int(st == cur.ERR_RANK) for _, _, st in outs)
+    elems = sum(A.numel() for A in As)
+    out = {"workload": "256 FP32 matrices, m,n ~ U[256,4096], r in {8,16,32,64}, spectra ratio ~ U[0.8,0.95]",
+           "matrices": len(As), "elements": elems,
+           "batched_ms": 1e3 * t_b, "batched_selections_per_s": len(As) / t_b,
+           "one_at_a_time_ms": 1e3 * t_s, "one_at_a_time_selections_per_s": len(As) / t_s,
+           "speedup": t_s / t_b, "items_equal_single": same, "items_rank_short": short, "status_worst": rc}
+    log(f"e2: batched {1e3 * t_b:.1f} ms, one at a time {1e3 * t_s:.1f} ms, equal {same}/{len(As)}")
+    del As
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +149,7 @@ def main():
                     help="build the C2 matrix on the host and copy it over (for counter runs)")
     ap.add_argument("--no-e1", action="store_true",
                     help="skip the reduced-precision residual figures on the tall FP32 workload")
+    ap.add_argument("--no-e2", action="store_true", help="skip the batched uneven-workload figures")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="one untimed device copy of this size, the calibration of the byte counters")
     args = ap.parse_args()
@@ -235,6 +273,9 @@ def main():
     e1 = None
     if not args.no_e1:
         e1 = bench_e1(cur, W, torch, dev)
+    e2 = None
+    if not args.no_e2:
+        e2 = bench_e2(cur, W, torch, dev)
 
     out = {
         "metric": "CUR selections/sec + swap-loop HBM GB/s at volume ratio >=0.99 vs FP64 oracle",
@@ -270,6 +311,7 @@ def main():
                       "refreshes": res["refreshes"], "nodes": res["nodes"], "logvol": res["logvol"]},
         "f32": f32,
         "e1_reduced_precision_residual": e1,
+        "e2_batched_uneven": e2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -635,6 +635,10 @@ __device__ void ctl_col_phase_reg(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   if (!ctl_build(nd, L, true, false)) {
     if (tid == 0) {
       int code = 108;  // numerically singular cross
+      for (int a = 0; a < r; ++a) {  // the cross, for diagnostics
+        nd.dbg[a] = (double)L.sI[a];
+        nd.dbg[64 + a] = (double)nd.Jc[L.sJp[a]];
+      }
       for (int a = 0; a < r; ++a) {
         if (L.sI[a] < 0 || L.sI[a] >= m) code = 132;
         if (L.sJp[a] < 0 || L.sJp[a] >= nc) code = 133;
@@ -925,6 +929,10 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
   // ---- serial steps until a pass is needed or the node is finished
   for (int guard = 0; guard < 64; ++guard) {
     const int mode = L.s.mode;
+    // every wavefront holds this step's mode before thread 0 may overwrite it
+    // (a late wavefront would otherwise take the next step's branch and run
+    // one barrier out of step with the rest of the block)
+    __syncthreads();
     if (mode == M_EXIT) break;
     if (mode == M_ROW_START) {
       ctl_sort_IJ(nd, L, r);
@@ -1166,7 +1174,14 @@ static void debug_report(cur_ctx ctx, const std::vector<Node>& h, const std::vec
                    "refreshes %d q %d nc %d nocap %d\n", l, k, nd.kind, nd.st, nd.err, nd.phase, nd.swaps,
                    nd.phases, nd.refreshes, nd.q, nd.nc, nd.nocap);
       std::vector<double> ring(4 * kDbgRing);
-      if (hipMemcpy(ring.data(), nd.dbg, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+      if (nd.err == 108 &&
+          hipMemcpy(ring.data(), nd.dbg, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+        std::fprintf(stderr, "  cross I:");
+        for (int a = 0; a < nd.r; ++a) std::fprintf(stderr, " %.0f", ring[a]);
+        std::fprintf(stderr, "\n  cross J:");
+        for (int a = 0; a < nd.r; ++a) std::fprintf(stderr, " %.0f", ring[64 + a]);
+        std::fprintf(stderr, "\n");
+      } else if (hipMemcpy(ring.data(), nd.dbg, sizeof(double) * ring.size(), hipMemcpyDeviceToHost) == hipSuccess) {
         const int n0 = nd.swaps > kDbgRing ? nd.swaps - kDbgRing : 0;
         for (int q = n0; q < nd.swaps; ++q) {
           const double* e = &ring[4 * (q % kDbgRing)];
@@ -1174,6 +1189,8 @@ static void debug_report(cur_ctx ctx, const std::vector<Node>& h, const std::vec
         }
       }
     }
+  const char* lvl = std::getenv("CUR_DEBUG");
+  if (!lvl || std::atoi(lvl) < 2) return;  // clocks only at level 2
   int wclk = 100000;  // ticks per ms of wall_clock64 (100 MHz)
   (void)hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, ctx->device);  // kHz
   for (size_t l = 0; l < lfirst.size(); ++l) {
@@ -1489,10 +1506,15 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     int32_t nodes = 0, phases = 0, refreshes = 0;
     int64_t swaps = 0;
     bool nocap = false;
+    std::string where;
     for (size_t l = 0; l < jb.count.size(); ++l)
       for (int k = 0; k < jb.count[l]; ++k) {
         const Node& nd = node(l, k);
-        if (nd.err) result = CUR_ERR_INTERNAL;
+        if (nd.err && result == CUR_OK) {
+          result = CUR_ERR_INTERNAL;
+          where = " (level " + std::to_string(l) + " node " + std::to_string(k) + " code " + std::to_string(nd.err) +
+                  " phase " + std::to_string(nd.phase) + " swaps " + std::to_string(nd.swaps) + ")";
+        }
         if (nd.kind == KIND_PROMOTED) continue;
         nodes++;
         phases += nd.phases;
@@ -1509,7 +1531,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         result = CUR_WARN_NOCONV;
       }
     } else {
-      set_error("singular cross met inside the swap loop");
+      set_error("singular cross met inside the swap loop" + where);
     }
     if (jb.info) {
       jb.info->rank = root.q;
