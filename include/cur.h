@@ -80,7 +80,10 @@ typedef struct {
   int32_t max_swaps;   /* swap budget per tree node; 0 -> 64 r                                   */
   int32_t prec;        /* cur_prec of the assembly/residual GEMMs (selection itself is exact)    */
   int32_t propose;     /* 0: no candidate proposal                                               */
-  int32_t reserved0;
+  int32_t groups;      /* node groups per tree level, each iterating on a stream of its own:
+                          0 -> autotuned per level shape (the first calls on a shape try 1, 2
+                          and 3 groups once each, later calls use the fastest); 1..3 fixed.
+                          The result does not depend on it.                                     */
   const void* mlp;     /* reserved (must be NULL when propose == 0)                              */
   uint64_t seed;       /* reserved                                                               */
   cur_trace* trace;    /* host pointer or NULL: per-node tree records                            */
@@ -167,20 +170,29 @@ typedef struct {
 cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items, const cur_opts* opts,
                               cur_status* per_item);
 
-/* Measurement counters of the selection's row passes (the bandwidth-bound
- * sweeps: ACA rank-1 updates, fresh interpolation matrices, Sherman-Morrison
- * row swaps).  While enabled, cur_select brackets every pass launch with HIP
- * events on the context's stream and counts on the device the algorithmic
- * bytes each pass must move (every element of the working columns it reads
- * plus every element it writes, once). */
+/* Measurement counters of the selection's row kernels.  While enabled,
+ * cur_select and cur_select_batched bracket every launch of the two row
+ * kernels with HIP events on the stream it is issued on, and count on the
+ * device the algorithmic bytes each launch must move (every element of the
+ * working columns it reads plus every element it writes, once):
+ *   pass   the streaming sweep: ACA rank-1 updates and Sherman-Morrison row
+ *          swaps over the m x (active columns) working matrix;
+ *   fresh  fresh interpolation matrices B = A(:, J) A(I, J)^-1.
+ * A launch is "busy" when at least one node of it moved bytes; the others
+ * found no node in their state and returned at once. */
 typedef struct {
-  int64_t launches;   /* pass launches timed                                   */
-  int64_t busy;       /* launches in which at least one node had work          */
-  double seconds;     /* summed event time of those launches                   */
-  double bytes;       /* summed algorithmic bytes                              */
+  int64_t launches;        /* pass launches timed                                 */
+  int64_t busy;            /* pass launches in which some node had work           */
+  double seconds;          /* summed event time of the pass launches              */
+  double bytes;            /* summed algorithmic bytes of the pass launches       */
+  int64_t fresh_launches;  /* the same four figures for the fresh kernel          */
+  int64_t fresh_busy;
+  double fresh_seconds;
+  double fresh_bytes;
 } cur_profile;
 
-/* Enable (1) or disable (0) the counters; enabling clears them. */
+/* Set the counters: 0 off, 1 the pass kernel, 2 the pass and fresh kernels
+ * (each timed launch adds two events to its stream); any call clears them. */
 cur_status cur_profile_enable(cur_ctx ctx, int enable);
 /* Copy the counters accumulated since enabling (host struct). */
 cur_status cur_profile_read(cur_ctx ctx, cur_profile* out);

@@ -47,7 +47,7 @@ class Trace(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("col_block", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("max_swaps", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("propose", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("propose", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("seed", ctypes.c_uint64),
                 ("trace", ctypes.POINTER(Trace))]
 
@@ -59,7 +59,8 @@ class Info(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("busy", ctypes.c_int64), ("seconds", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("fresh_launches", ctypes.c_int64), ("fresh_busy", ctypes.c_int64),
+                ("fresh_seconds", ctypes.c_double), ("fresh_bytes", ctypes.c_double)]
 
 
 class Item(ctypes.Structure):
@@ -160,9 +161,10 @@ def _matrix(A):
     return A.shape[0], A.shape[1], A.stride(0)
 
 
-def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None) -> Opts:
+def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None, groups=0) -> Opts:
     o = Opts()
     lib().cur_opts_init(ctypes.byref(o))
+    o.groups = int(groups)
     o.col_block = int(col_block)
     o.tau = float(tau)
     o.max_swaps = int(max_swaps)
@@ -183,7 +185,7 @@ def tree_size(n: int, w: int) -> int:
 
 
 def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, trace: bool = False,
-           allow=(OK, WARN_NOCONV, ERR_RANK)):
+           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0):
     """Select r rows I and r columns J of the device matrix A (cur_select)."""
     torch = _torch()
     m, n, lda = _matrix(A)
@@ -202,7 +204,7 @@ def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, 
                 "I": np.zeros((N, r), dtype=np.int64), "J": np.zeros((N, r), dtype=np.int64)}
         tr = Trace(N, 0, host["meta"].ctypes.data, host["vol_m"].ctypes.data,
                    host["I"].ctypes.data, host["J"].ctypes.data)
-    o = make_opts(col_block, tau, max_swaps, trace=tr)
+    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups)
     rc = lib().cur_select(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
                           ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                           ctypes.byref(info))
@@ -251,18 +253,21 @@ def residual(A, C, U, R, prec: int = PREC_NATIVE):
     return cheb.value, fro.value
 
 
-def profile_enable(enable: bool = True, device=None):
-    """Turn the pass timing / algorithmic-byte counters on (cleared) or off."""
-    _check(lib().cur_profile_enable(context(device), 1 if enable else 0))
+def profile_enable(enable=True, device=None):
+    """Set the row-kernel timing / algorithmic-byte counters (cleared): False
+    or 0 off, True or 1 the streaming pass kernel, 2 also the fresh kernel."""
+    _check(lib().cur_profile_enable(context(device), int(enable)))
 
 
 def profile_read(device=None) -> dict:
     p = Profile()
     _check(lib().cur_profile_read(context(device), ctypes.byref(p)))
-    return {"launches": p.launches, "seconds": p.seconds, "bytes": p.bytes}
+    return {"launches": p.launches, "busy": p.busy, "seconds": p.seconds, "bytes": p.bytes,
+            "fresh_launches": p.fresh_launches, "fresh_busy": p.fresh_busy,
+            "fresh_seconds": p.fresh_seconds, "fresh_bytes": p.fresh_bytes}
 
 
-def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0):
+def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, groups: int = 0):
     """Independent selections of several device matrices (cur_select_batched)."""
     torch = _torch()
     cnt = len(As)
@@ -275,7 +280,7 @@ def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int 
         items[k] = Item(_dtype_code(A), int(r), A.data_ptr(), m, n, lda, I.data_ptr(), J.data_ptr())
         outs.append((I, J))
     per = (ctypes.c_int * max(cnt, 1))()
-    o = make_opts(col_block, tau, max_swaps)
+    o = make_opts(col_block, tau, max_swaps, groups=groups)
     ctx = context(As[0].device.index if cnt else None)
     rc = lib().cur_select_batched(ctx, cnt, items, ctypes.byref(o), per)
     _check(rc, (OK, WARN_NOCONV, ERR_RANK))

@@ -74,6 +74,7 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.max_swaps == 0) o.max_swaps = 64 * r;
   if (o.prec < CUR_PREC_NATIVE || o.prec > CUR_PREC_FP8) return arg_error("prec out of range");
   if (o.propose != 0) return arg_error("propose must be 0 in this build");
+  if (o.groups < 0 || o.groups > 3) return arg_error("groups must be 0 (autotuned) or 1..3");
   if (o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
   if (o.trace) {
     int64_t b = n / o.col_block;
@@ -140,7 +141,10 @@ cur_status cur_create(cur_ctx* out, int device, void* hip_stream) {
   c->prof_on = 0;
   c->prof_bytes = nullptr;
   c->prof_ev = new std::vector<hipEvent_t>();
+  c->prof_kind = new std::vector<int>();
   std::memset(&c->prof, 0, sizeof(c->prof));
+  c->groups_ready = 0;
+  c->tune = new std::vector<cur::TuneEntry>();
   c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
   c->own_stream = false;
   e = hipHostMalloc((void**)&c->host_flag, 64, hipHostMallocDefault);
@@ -166,7 +170,17 @@ cur_status cur_destroy(cur_ctx ctx) {
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   if (ctx->prof_bytes) hipFree(ctx->prof_bytes);
   for (hipEvent_t e : *ctx->prof_ev) hipEventDestroy(e);
+  if (ctx->groups_ready) {
+    for (int g = 0; g < 4; ++g) {
+      hipStreamSynchronize(ctx->gstream[g]);
+      hipStreamDestroy(ctx->gstream[g]);
+      hipEventDestroy(ctx->gjoin[g]);
+    }
+    hipEventDestroy(ctx->gfork);
+  }
   delete ctx->prof_ev;
+  delete ctx->prof_kind;
+  delete ctx->tune;
   delete ctx;
   return CUR_OK;
 }
@@ -220,26 +234,18 @@ cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, 
 
 cur_status cur_profile_enable(cur_ctx ctx, int enable) {
   if (!ctx) return arg_error("ctx is NULL");
+  if (enable < 0 || enable > 2) return arg_error("enable must be 0, 1 or 2");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
-  if (enable && !ctx->prof_bytes) CUR_HIP_CHECK(hipMalloc((void**)&ctx->prof_bytes, 64));
-  if (enable) {
-    CUR_HIP_CHECK(hipMemsetAsync(ctx->prof_bytes, 0, 64, ctx->stream));
-    CUR_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-  }
+  if (enable && !ctx->prof_bytes)
+    CUR_HIP_CHECK(hipMalloc((void**)&ctx->prof_bytes, sizeof(unsigned long long) * cur::kProfSlots));
   std::memset(&ctx->prof, 0, sizeof(ctx->prof));
-  ctx->prof_on = enable ? 1 : 0;
+  ctx->prof_on = enable;
   return CUR_OK;
 }
 
 cur_status cur_profile_read(cur_ctx ctx, cur_profile* out) {
   if (!ctx || !out) return arg_error("ctx and out must be non-NULL");
-  *out = ctx->prof;
-  if (ctx->prof_bytes) {
-    unsigned long long b = 0;
-    CUR_HIP_CHECK(hipMemcpyAsync(&b, ctx->prof_bytes, sizeof(b), hipMemcpyDeviceToHost, ctx->stream));
-    CUR_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    out->bytes = (double)b;
-  }
+  *out = ctx->prof;  // accumulated at the end of every profiled selection
   return CUR_OK;
 }
 

@@ -101,6 +101,16 @@ const char* last_error();
 }  // namespace cur
 
 // Context (opaque to callers).
+namespace cur {
+// One entry of the launch-shape autotuner: a tree level's shape and the wall
+// time measured for each node-group count tried on it.
+struct TuneEntry {
+  int64_t key[6];  // FP64, r bucket, nodes, row tiles, rows, leaf level
+  double ms[3];    // wall time per candidate group count (1, 2, 3)
+  int tried;       // candidates measured so far
+};
+}  // namespace cur
+
 struct cur_ctx_s {
   int device;
   hipStream_t stream;
@@ -112,9 +122,17 @@ struct cur_ctx_s {
   int last_pinv;        // cur_assemble used the pseudo-inverse
   // measurement counters (cur_profile_*)
   int prof_on;
-  unsigned long long* prof_bytes;   // device counter of algorithmic pass bytes
+  unsigned long long* prof_bytes;   // device byte slots, one per timed launch
   std::vector<hipEvent_t>* prof_ev; // event pairs of the current selection
+  std::vector<int>* prof_kind;      // per pair: 0 pass, 1 fresh
   cur_profile prof;
+  // node groups of a tree level, each iterating on a stream of its own
+  // (created on first use, default priority)
+  int groups_ready;
+  hipStream_t gstream[4];
+  hipEvent_t gfork;
+  hipEvent_t gjoin[4];
+  std::vector<cur::TuneEntry>* tune;  // autotuner cache of this context
 };
 
 namespace cur {
@@ -133,8 +151,12 @@ struct Arena {
 };
 cur_status ensure_arena(cur_ctx ctx, size_t bytes);
 
-// One row pass over every active node of a level (pass.hip); rb is the
-// register bucket of r (32, 64 or 128), prof the device byte counter or null.
+// The row kernels over every node of a level in their state (pass.hip): the
+// fresh interpolation matrix, and the streaming pass (ACA step or row swap).
+// rb is the register bucket of r (32, 64 or 128), prof the launch's device
+// byte slot or null.
+constexpr int kProfSlots = 1 << 16;  // timed launches per selection call
+void fresh_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 void pass_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 
 // Reduced-precision residual (residual_mp.hip): scratch bytes, tile count, and

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -119,8 +120,7 @@ __global__ void k_leaf_init(Node* nodes) {
 // source map of the panel, and the starting (I, J) from the child of larger
 // volume (exact tie: left), or prepare an ACA start when both children are
 // rank-short.
-__global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node* prev,
-                                                         int32_t* done) {
+__global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node* prev) {
   Node& nd = nodes[blockIdx.x];
   const int tid = threadIdx.x;
   const int r = nd.r;
@@ -138,8 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
       nd.vol_m = c.vol_m;
       nd.vol_e = c.vol_e;
       nd.err = c.err;
-      nd.st = ST_DONE;
-      atomicAdd(done, 1);
+      nd.st = ST_DONE;  // counted by the level's start-up controller launch
     }
     return;
   }
@@ -200,8 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
       nd.na = c;
       if (nd.steps == 0) {
         nd.is_short = 1;
-        nd.st = ST_DONE;
-        atomicAdd(done, 1);
+        nd.st = ST_DONE;  // counted by the level's start-up controller launch
       } else {
         nd.st = ST_ACA;
       }
@@ -794,7 +792,11 @@ __device__ void ctl_col_phase_reg(Node& nd, CtlLds<T, RMAX>& L, double lim) {
 template <typename T, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, int startup) {
   Node& nd = nodes[blockIdx.x];
-  if (nd.st == ST_DONE) return;
+  if (nd.st == ST_DONE) {
+    // a node finished by its initialization is counted once, at start-up
+    if (startup && threadIdx.x == 0) atomicAdd(done, 1);
+    return;
+  }
   // the start-up launch only opens swap loops; pass states wait for their pass
   if (startup && nd.st != ST_START_SWAP) return;
   __shared__ CtlLds<T, RMAX> L;
@@ -1074,10 +1076,6 @@ static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, hipSt
   hipLaunchKernelGGL((k_ctl<T, RMAX>), dim3(count), dim3(kThreads), 0, s, nodes, done, startup);
 }
 
-template <typename T>
-static void pass_any(int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s) {
-  pass_launch(std::is_same<T, double>::value, rb, nodes, count, tiles, prof, s);
-}
 
 // Event pair around a pass launch when the measurement counters are on.
 static hipEvent_t prof_event(cur_ctx ctx, size_t idx) {
@@ -1089,6 +1087,35 @@ static hipEvent_t prof_event(cur_ctx ctx, size_t idx) {
   }
   return ev[idx];
 }
+// One launch of a row kernel (kind 0: the streaming pass, 1: fresh B) on
+// stream s; with the counters on, bracketed by an event pair and given its
+// own device byte slot.
+template <typename T>
+static void row_launch(cur_ctx ctx, int kind, int rb, Node* nodes, int count, int tiles, hipStream_t s,
+                       size_t& prof_used) {
+  const bool f64 = std::is_same<T, double>::value;
+  auto go = [&](unsigned long long* slot) {
+    if (kind == 1) fresh_launch(f64, rb, nodes, count, tiles, slot, s);
+    else pass_launch(f64, rb, nodes, count, tiles, slot, s);
+  };
+  const size_t pair = prof_used / 2;
+  if (ctx->prof_on < (kind == 1 ? 2 : 1) || pair >= (size_t)kProfSlots) {
+    go(nullptr);
+    return;
+  }
+  hipEvent_t e0 = prof_event(ctx, prof_used), e1 = prof_event(ctx, prof_used + 1);
+  if (!e0 || !e1) {
+    go(nullptr);
+    return;
+  }
+  (void)hipEventRecord(e0, s);
+  go(ctx->prof_bytes + pair);
+  (void)hipEventRecord(e1, s);
+  if (ctx->prof_kind->size() <= pair) ctx->prof_kind->resize(pair + 1);
+  (*ctx->prof_kind)[pair] = kind;
+  prof_used += 2;
+}
+
 template <typename T>
 static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
   if (rb == 32) launch_ctl<T, 32>(nodes, count, done, startup, s);
@@ -1096,35 +1123,110 @@ static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, 
   else launch_ctl<T, 128>(nodes, count, done, startup, s);
 }
 
+// Streams and events of the node groups, created once per context.
+constexpr int kMaxGroups = 4;
+static cur_status ensure_groups(cur_ctx ctx) {
+  if (ctx->groups_ready) return CUR_OK;
+  for (int g = 0; g < kMaxGroups; ++g) {
+    CUR_HIP_CHECK(hipStreamCreateWithFlags(&ctx->gstream[g], hipStreamNonBlocking));
+    CUR_HIP_CHECK(hipEventCreateWithFlags(&ctx->gjoin[g], hipEventDisableTiming));
+  }
+  CUR_HIP_CHECK(hipEventCreateWithFlags(&ctx->gfork, hipEventDisableTiming));
+  ctx->groups_ready = 1;
+  return CUR_OK;
+}
+
+// Launch-shape autotuner.  The node-group count of a level changes only how
+// the level's launches are spread over streams, never a result, so it is
+// chosen by measurement: the first calls on a level shape try each candidate
+// once (the level's host wall time, which ends with a stream synchronization),
+// later calls use the fastest.  The cache lives in the context.
+static const int kGroupCand[3] = {1, 2, 3};
+
+static TuneEntry* tune_find(cur_ctx ctx, const int64_t key[6]) {
+  for (TuneEntry& e : *ctx->tune)
+    if (std::equal(key, key + 6, e.key)) return &e;
+  TuneEntry e;
+  std::copy(key, key + 6, e.key);
+  for (double& v : e.ms) v = -1.0;
+  e.tried = 0;
+  ctx->tune->push_back(e);
+  return &ctx->tune->back();
+}
+
+// Group count for a level: `fixed` when the caller set one, else the next
+// untried candidate (its index in *cand), else the fastest one measured.
+static int tune_pick(cur_ctx ctx, const int64_t key[6], int fixed, int* cand) {
+  *cand = -1;
+  if (fixed > 0) return fixed;
+  TuneEntry* e = tune_find(ctx, key);
+  if (e->tried < 3) {
+    *cand = e->tried;
+    return kGroupCand[e->tried];
+  }
+  int best = 0;
+  for (int k = 1; k < 3; ++k)
+    if (e->ms[k] < e->ms[best]) best = k;
+  return kGroupCand[best];
+}
+
+static void tune_record(cur_ctx ctx, const int64_t key[6], int cand, std::chrono::steady_clock::time_point t0) {
+  if (cand < 0) return;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  TuneEntry* e = tune_find(ctx, key);
+  if (e->tried == cand) {
+    e->ms[cand] = ms;
+    e->tried++;
+  }
+}
+
 // Runs pass/ctl iterations on one level until all `count` nodes are done.
+// With groups > 1 the level's nodes are split into that many contiguous
+// groups, each iterating on a stream of its own with its own done counter
+// (d_done[g]) and poll: a node whose controller step is long (an LU rebuild,
+// a column phase) then holds back only its own group, and its latency-bound
+// controller launch overlaps the other groups' streaming passes.  Groups
+// share no node data; all ordering is by stream order within a group.
 template <typename T>
 static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int tiles, int32_t* d_done,
-                            int64_t max_iters, size_t& prof_used) {
-  hipStream_t s = ctx->stream;
+                            int64_t max_iters, size_t& prof_used, int groups) {
+  const int G = std::max(1, std::min(std::min(groups, count), kMaxGroups));
+  hipStream_t gs[kMaxGroups];
+  hipEvent_t ev[kMaxGroups];
+  int off[kMaxGroups + 1];
+  bool pending[kMaxGroups], fin[kMaxGroups];
+  for (int g = 0; g <= G; ++g) off[g] = (int)((int64_t)count * g / G);
+  if (G == 1) {
+    gs[0] = ctx->stream;
+  } else {
+    cur_status st = ensure_groups(ctx);
+    if (st != CUR_OK) return st;
+    CUR_HIP_CHECK(hipEventRecord(ctx->gfork, ctx->stream));
+    for (int g = 0; g < G; ++g) {
+      gs[g] = ctx->gstream[g];
+      CUR_HIP_CHECK(hipStreamWaitEvent(gs[g], ctx->gfork, 0));
+    }
+  }
+  for (int g = 0; g < G; ++g) {
+    CUR_HIP_CHECK(hipEventCreateWithFlags(&ev[g], hipEventDisableTiming));
+    pending[g] = fin[g] = false;
+  }
   volatile int32_t* h = ctx->host_flag;
-  hipEvent_t ev;
-  CUR_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  ctl_any<T>(rb, nodes, count, d_done, 1, s);  // start-up decisions
+  for (int g = 0; g < G; ++g)  // start-up decisions
+    ctl_any<T>(rb, nodes + off[g], off[g + 1] - off[g], d_done + g, 1, gs[g]);
   const int K = 4;
   int64_t it = 0;
-  bool pending = false;
   cur_status rc = CUR_OK;
   for (;;) {
-    for (int j = 0; j < K; ++j) {
-      if (ctx->prof_on) {
-        hipEvent_t e0 = prof_event(ctx, prof_used), e1 = prof_event(ctx, prof_used + 1);
-        if (e0 && e1) {
-          (void)hipEventRecord(e0, s);
-          pass_any<T>(rb, nodes, count, tiles, ctx->prof_bytes, s);
-          (void)hipEventRecord(e1, s);
-          prof_used += 2;
-        } else {
-          pass_any<T>(rb, nodes, count, tiles, ctx->prof_bytes, s);
-        }
-      } else {
-        pass_any<T>(rb, nodes, count, tiles, nullptr, s);
+    for (int g = 0; g < G; ++g) {
+      if (fin[g]) continue;
+      Node* gn = nodes + off[g];
+      const int gc = off[g + 1] - off[g];
+      for (int j = 0; j < K; ++j) {
+        row_launch<T>(ctx, 1, rb, gn, gc, tiles, gs[g], prof_used);
+        row_launch<T>(ctx, 0, rb, gn, gc, tiles, gs[g], prof_used);
+        ctl_any<T>(rb, gn, gc, d_done + g, 0, gs[g]);
       }
-      ctl_any<T>(rb, nodes, count, d_done, 0, s);
     }
     it += K;
     hipError_t e = hipGetLastError();
@@ -1133,32 +1235,47 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
       rc = CUR_ERR_DEVICE;
       break;
     }
-    if (pending) {
-      e = hipEventSynchronize(ev);
+    bool all = true;
+    for (int g = 0; g < G && rc == CUR_OK; ++g) {
+      if (fin[g]) continue;
+      if (pending[g]) {
+        e = hipEventSynchronize(ev[g]);
+        if (e != hipSuccess) {
+          set_error(std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+          rc = CUR_ERR_DEVICE;
+          break;
+        }
+        if (h[g] >= off[g + 1] - off[g]) {  // -1 (copy not landed) reads as "not done"
+          fin[g] = true;
+          continue;
+        }
+      }
+      all = false;
+      h[g] = -1;
+      e = hipMemcpyAsync((void*)(h + g), d_done + g, sizeof(int32_t), hipMemcpyDeviceToHost, gs[g]);
+      if (e == hipSuccess) e = hipEventRecord(ev[g], gs[g]);
       if (e != hipSuccess) {
-        set_error(std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        set_error(std::string("poll: ") + hipGetErrorString(e));
         rc = CUR_ERR_DEVICE;
         break;
       }
-      if (*h >= count) break;  // -1 (copy not landed) reads as "not done"
+      pending[g] = true;
     }
-    *h = -1;
-    e = hipMemcpyAsync((void*)h, d_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(ev, s);
-    if (e != hipSuccess) {
-      set_error(std::string("poll: ") + hipGetErrorString(e));
-      rc = CUR_ERR_DEVICE;
-      break;
-    }
-    pending = true;
+    if (rc != CUR_OK || all) break;
     if (it > max_iters) {
       set_error("selection did not converge within the iteration bound");
       rc = CUR_ERR_INTERNAL;
       break;
     }
   }
-  (void)hipStreamSynchronize(s);
-  (void)hipEventDestroy(ev);
+  if (G > 1) {
+    for (int g = 0; g < G; ++g) {
+      (void)hipEventRecord(ctx->gjoin[g], gs[g]);
+      (void)hipStreamWaitEvent(ctx->stream, ctx->gjoin[g], 0);
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int g = 0; g < G; ++g) (void)hipEventDestroy(ev[g]);
   return rc;
 }
 
@@ -1438,6 +1555,15 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   CUR_HIP_CHECK(hipMemcpyAsync(d_nodes, h.data(), sizeof(Node) * total, hipMemcpyHostToDevice, s));
   CUR_HIP_CHECK(hipMemcpyAsync(d_roots, roots.data(), sizeof(RootOut) * roots.size(), hipMemcpyHostToDevice, s));
   CUR_HIP_CHECK(hipMemsetAsync(d_done, 0, 4096, s));
+  if (ctx->prof_on) CUR_HIP_CHECK(hipMemsetAsync(ctx->prof_bytes, 0, sizeof(unsigned long long) * kProfSlots, s));
+
+  int fixed_groups = 0;
+  for (const TreeJob<T>& jb : jobs)
+    if (jb.active) {
+      fixed_groups = jb.o.groups;
+      break;
+    }
+  const int f64 = std::is_same<T, double>::value ? 1 : 0;
 
   // ---- level 0: every leaf of every tree
   size_t prof_used = 0;
@@ -1446,7 +1572,12 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     hipLaunchKernelGGL(k_leaf_init, dim3(b), dim3(kThreads), 0, s, d_nodes);
     hipLaunchKernelGGL((k_panel_from_A<T>), dim3((maxm + kTR - 1) / kTR, (leafmax + 63) / 64, b), dim3(kThreads),
                        0, s, d_nodes);
-    cur_status rc = run_level<T>(ctx, rb, d_nodes, b, maxtiles, d_done + 0, iter_bound, prof_used);
+    const int64_t key[6] = {f64, rb, b, maxtiles, maxm, 1};
+    int cand = -1;
+    const int groups = tune_pick(ctx, key, fixed_groups, &cand);
+    const auto t0 = std::chrono::steady_clock::now();
+    cur_status rc = run_level<T>(ctx, rb, d_nodes, b, maxtiles, d_done + 0, iter_bound, prof_used, groups);
+    if (rc == CUR_OK) tune_record(ctx, key, cand, t0);
     if (rc != CUR_OK) return rc;
   }
 
@@ -1462,10 +1593,15 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         lt = std::max(lt, jb.ntiles);
       }
     int32_t* dd = d_done + 16 * l;
-    hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev, dd);
+    hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev);
     const int gx = (int)std::min<int64_t>((lm + kThreads - 1) / kThreads, 64);
     hipLaunchKernelGGL((k_panel_build<T>), dim3(gx, 2 * rmax, cnt), dim3(kThreads), 0, s, cur, prev);
-    cur_status rc = run_level<T>(ctx, rb, cur, cnt, lt, dd, iter_bound, prof_used);
+    const int64_t key[6] = {f64, rb, cnt, lt, lm, 0};
+    int cand = -1;
+    const int groups = tune_pick(ctx, key, fixed_groups, &cand);
+    const auto t0 = std::chrono::steady_clock::now();
+    cur_status rc = run_level<T>(ctx, rb, cur, cnt, lt, dd, iter_bound, prof_used, groups);
+    if (rc == CUR_OK) tune_record(ctx, key, cand, t0);
     if (rc != CUR_OK) return rc;
   }
 
@@ -1481,13 +1617,25 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     CUR_HIP_CHECK(hipMemcpyAsync(eJ.data(), d_expJ, sizeof(int64_t) * eJ.size(), hipMemcpyDeviceToHost, s));
   }
   CUR_HIP_CHECK(hipStreamSynchronize(s));
-  if (ctx->prof_on) {
+  if (ctx->prof_on && prof_used >= 2) {
+    const size_t pairs = prof_used / 2;
+    std::vector<unsigned long long> hb(pairs);
+    CUR_HIP_CHECK(hipMemcpy(hb.data(), ctx->prof_bytes, sizeof(unsigned long long) * pairs, hipMemcpyDeviceToHost));
     std::vector<hipEvent_t>& ev = *ctx->prof_ev;
-    for (size_t k = 0; k + 1 < prof_used; k += 2) {
+    for (size_t k = 0; k < pairs; ++k) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) {
-        ctx->prof.seconds += 1e-3 * ms;
-        ctx->prof.launches += 1;
+      if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) continue;
+      cur_profile& p = ctx->prof;
+      if ((*ctx->prof_kind)[k] == 1) {
+        p.fresh_launches += 1;
+        p.fresh_busy += hb[k] > 0;
+        p.fresh_seconds += 1e-3 * ms;
+        p.fresh_bytes += (double)hb[k];
+      } else {
+        p.launches += 1;
+        p.busy += hb[k] > 0;
+        p.seconds += 1e-3 * ms;
+        p.bytes += (double)hb[k];
       }
     }
   }

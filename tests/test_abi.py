@@ -34,13 +34,15 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cur.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(cur_opts), sizeof(cur_info),'
-                   ' sizeof(cur_item), sizeof(cur_trace), offsetof(cur_opts, trace), offsetof(cur_item, I));}\n')
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cur_opts), sizeof(cur_info),'
+                   ' sizeof(cur_item), sizeof(cur_trace), offsetof(cur_opts, trace), offsetof(cur_item, I),'
+                   ' sizeof(cur_profile), offsetof(cur_opts, groups));}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(cur.Opts), ctypes.sizeof(cur.Info), ctypes.sizeof(cur.Item),
-            ctypes.sizeof(cur.Trace), cur.Opts.trace.offset, cur.Item.I.offset]
+            ctypes.sizeof(cur.Trace), cur.Opts.trace.offset, cur.Item.I.offset,
+            ctypes.sizeof(cur.Profile), cur.Opts.groups.offset]
     assert got == want
 
 
@@ -66,6 +68,7 @@ def test_select_argument_errors_on_host(kw, msg):
     ("col_block", 2, "col_block must be >= r"), ("col_block", -1, "col_block"),
     ("tau", -1.0, "tau"), ("max_swaps", -3, "max_swaps"), ("prec", 9, "prec"),
     ("propose", 1, "propose"), ("struct_size", 8, "struct_size"),
+    ("groups", 4, "groups"), ("groups", -1, "groups"),
 ])
 def test_select_option_errors_on_host(field, value, msg):
     o = cur.make_opts()

@@ -263,3 +263,29 @@ def test_select_batched_mixed_trees_match_single(orc):
             np.testing.assert_array_equal(J.cpu().numpy(), o["J"])
         if seed == 0:
             assert st == cur.ERR_RANK
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_node_groups_do_not_change_the_selection(orc, dt):
+    """Splitting each tree level into 1, 2 or 3 node groups on their own
+    streams, fixed or chosen by the autotuner (whose first calls try each
+    count), gives the same selection bit for bit; 24 leaves make levels of
+    24, 12, 6, 3, 2, 1 nodes, so a promoted odd node lands in a group."""
+    m, n, r, seed = 1024, 1536, 32, 21
+    say(f"case node groups m={m} n={n} r={r} seed={seed} {dt}")
+    A = torch.from_numpy(W.gaussian(m, n, seed)).to(DEV).to(dt)
+    ref = cur.select(A, r, groups=1)
+    for groups in (2, 3, 0, 0, 0, 0):
+        g = cur.select(A, r, groups=groups)
+        assert g["status"] == ref["status"]
+        np.testing.assert_array_equal(g["I"].cpu().numpy(), ref["I"].cpu().numpy())
+        np.testing.assert_array_equal(g["J"].cpu().numpy(), ref["J"].cpu().numpy())
+    if dt == torch.float64:
+        o = orc.select(A.cpu().numpy(), r)
+        np.testing.assert_array_equal(ref["I"].cpu().numpy(), o["I"])
+        np.testing.assert_array_equal(ref["J"].cpu().numpy(), o["J"])
+    outs1, _ = cur.select_batched([A, A[:700, :900].contiguous()], [r, 16], groups=1)
+    outs3, _ = cur.select_batched([A, A[:700, :900].contiguous()], [r, 16], groups=3)
+    for (I1, J1, s1), (I3, J3, s3) in zip(outs1, outs3):
+        assert s1 == s3
+        assert torch.equal(I1, I3) and torch.equal(J1, J3)
