@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--no-e1", action="store_true",
                     help="skip the reduced-precision residual figures on the tall FP32 workload")
     ap.add_argument("--no-e2", action="store_true", help="skip the batched uneven-workload figures")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of the launch autotuner cache: loaded before the run when it exists, "
+                         "written at the end (profiling runs reuse the tuned launch shapes)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="one untimed device copy of this size, the calibration of the byte counters")
     args = ap.parse_args()
@@ -168,6 +171,10 @@ def main():
     from paper_2502_11017_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        with open(args.tune_cache) as f:
+            cur.tune_import(json.load(f))
+        log(f"autotuner cache loaded from {args.tune_cache}")
     m = n = 8192
     r = 64
     if args.host_matrix:
@@ -319,6 +326,9 @@ def main():
         "e2_batched_uneven": e2,
         "cpu_baseline": cpu,
     }
+    if args.tune_cache:
+        with open(args.tune_cache, "w") as f:
+            json.dump(cur.tune_export(), f)
     print(json.dumps(out), flush=True)
 
 

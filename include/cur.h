@@ -191,6 +191,24 @@ typedef struct {
   double fresh_bytes;
 } cur_profile;
 
+/* The launch-shape autotuner cache of a context (cur_opts.groups == 0).  One
+ * entry per tree-level shape: key = {FP64 (1) or FP32 (0), r bucket (32, 64
+ * or 128), nodes in the level, row tiles per node, rows, leaf level (1/0)};
+ * ms = wall time measured for 1, 2 and 3 node groups (tried of them so far);
+ * groups = the count in use: the fastest once all three are measured, an
+ * imported choice, or 0 while still exploring.  Export copies up to `cap`
+ * entries to a host array (count = entries in the cache); import replaces the
+ * cache, and an entry with groups > 0 is then used as is, with no exploring.
+ * Lets a caller keep tuned choices across processes. */
+typedef struct {
+  int64_t key[6];
+  double ms[3];
+  int32_t tried;
+  int32_t groups;
+} cur_tune_entry;
+cur_status cur_tune_export(cur_ctx ctx, cur_tune_entry* out, int32_t cap, int32_t* count);
+cur_status cur_tune_import(cur_ctx ctx, const cur_tune_entry* in, int32_t count);
+
 /* Set the counters: 0 off, 1 the pass kernel, 2 the pass and fresh kernels
  * (each timed launch adds two events to its stream); any call clears them. */
 cur_status cur_profile_enable(cur_ctx ctx, int enable);

@@ -29,7 +29,7 @@ TRACE_FIELDS = ("level", "index", "q", "short", "promoted", "nocap", "swaps", "p
 
 EXPORTS = ("cur_opts_init", "cur_create", "cur_destroy", "cur_strerror", "cur_last_error",
            "cur_select", "cur_assemble", "cur_residual", "cur_select_batched",
-           "cur_profile_enable", "cur_profile_read")
+           "cur_profile_enable", "cur_profile_read", "cur_tune_export", "cur_tune_import")
 
 
 class CurError(RuntimeError):
@@ -55,6 +55,11 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int32), ("nodes", ctypes.c_int32), ("phases", ctypes.c_int32),
                 ("refreshes", ctypes.c_int32), ("swaps", ctypes.c_int64), ("logvol", ctypes.c_double)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_int64 * 6), ("ms", ctypes.c_double * 3), ("tried", ctypes.c_int32),
+                ("groups", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -106,6 +111,10 @@ def lib():
         L.cur_profile_enable.restype = ctypes.c_int
         L.cur_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
         L.cur_profile_read.restype = ctypes.c_int
+        L.cur_tune_export.argtypes = [P, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)]
+        L.cur_tune_export.restype = ctypes.c_int
+        L.cur_tune_import.argtypes = [P, ctypes.POINTER(TuneEntry), i32]
+        L.cur_tune_import.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -265,6 +274,26 @@ def profile_read(device=None) -> dict:
     return {"launches": p.launches, "busy": p.busy, "seconds": p.seconds, "bytes": p.bytes,
             "fresh_launches": p.fresh_launches, "fresh_busy": p.fresh_busy,
             "fresh_seconds": p.fresh_seconds, "fresh_bytes": p.fresh_bytes}
+
+
+def tune_export(device=None) -> list:
+    """The context's launch-shape autotuner cache as a list of dicts."""
+    ctx = context(device)
+    n = ctypes.c_int32(0)
+    _check(lib().cur_tune_export(ctx, None, 0, ctypes.byref(n)))
+    buf = (TuneEntry * max(n.value, 1))()
+    _check(lib().cur_tune_export(ctx, buf, n.value, ctypes.byref(n)))
+    return [{"key": list(e.key), "ms": list(e.ms), "tried": e.tried, "groups": e.groups}
+            for e in buf[:n.value]]
+
+
+def tune_import(entries, device=None):
+    """Replace the context's autotuner cache (entries as from tune_export)."""
+    buf = (TuneEntry * max(len(entries), 1))()
+    for k, e in enumerate(entries):
+        buf[k] = TuneEntry((ctypes.c_int64 * 6)(*e["key"]), (ctypes.c_double * 3)(*e["ms"]),
+                           int(e["tried"]), int(e["groups"]))
+    _check(lib().cur_tune_import(context(device), buf, len(entries)))
 
 
 def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, groups: int = 0):

@@ -2,6 +2,7 @@
 // context and workspace management, error strings.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -230,6 +231,40 @@ cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, 
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
   return residual_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
+}
+
+cur_status cur_tune_export(cur_ctx ctx, cur_tune_entry* out, int32_t cap, int32_t* count) {
+  if (!ctx || !count) return arg_error("ctx and count must be non-NULL");
+  if (cap < 0 || (cap > 0 && !out)) return arg_error("out must hold cap >= 0 entries");
+  const std::vector<cur::TuneEntry>& t = *ctx->tune;
+  *count = (int32_t)t.size();
+  for (int32_t k = 0; k < cap && k < (int32_t)t.size(); ++k) {
+    const cur::TuneEntry& e = t[k];
+    cur_tune_entry& o = out[k];
+    std::copy(e.key, e.key + 6, o.key);
+    std::copy(e.ms, e.ms + 3, o.ms);
+    o.tried = e.tried;
+    o.groups = e.fixed > 0 ? e.fixed : (e.tried >= 3 ? cur::tune_best(e) : 0);
+  }
+  return CUR_OK;
+}
+
+cur_status cur_tune_import(cur_ctx ctx, const cur_tune_entry* in, int32_t count) {
+  if (!ctx) return arg_error("ctx is NULL");
+  if (count < 0 || (count > 0 && !in)) return arg_error("in must hold count >= 0 entries");
+  std::vector<cur::TuneEntry> t;
+  for (int32_t k = 0; k < count; ++k) {
+    const cur_tune_entry& i = in[k];
+    if (i.groups < 0 || i.groups > 3 || i.tried < 0 || i.tried > 3) return arg_error("tune entry out of range");
+    cur::TuneEntry e;
+    std::copy(i.key, i.key + 6, e.key);
+    std::copy(i.ms, i.ms + 3, e.ms);
+    e.tried = i.tried;
+    e.fixed = i.groups;
+    t.push_back(e);
+  }
+  *ctx->tune = t;
+  return CUR_OK;
 }
 
 cur_status cur_profile_enable(cur_ctx ctx, int enable) {

@@ -108,6 +108,7 @@ struct TuneEntry {
   int64_t key[6];  // FP64, r bucket, nodes, row tiles, rows, leaf level
   double ms[3];    // wall time per candidate group count (1, 2, 3)
   int tried;       // candidates measured so far
+  int fixed;       // > 0: use this group count (an imported choice)
 };
 }  // namespace cur
 
@@ -156,6 +157,7 @@ cur_status ensure_arena(cur_ctx ctx, size_t bytes);
 // rb is the register bucket of r (32, 64 or 128), prof the launch's device
 // byte slot or null.
 constexpr int kProfSlots = 1 << 16;  // timed launches per selection call
+int tune_best(const TuneEntry& e);  // fastest group count of an explored entry
 void fresh_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 void pass_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 

@@ -1150,8 +1150,17 @@ static TuneEntry* tune_find(cur_ctx ctx, const int64_t key[6]) {
   std::copy(key, key + 6, e.key);
   for (double& v : e.ms) v = -1.0;
   e.tried = 0;
+  e.fixed = 0;
   ctx->tune->push_back(e);
   return &ctx->tune->back();
+}
+
+// Fastest measured candidate of a fully explored entry.
+int tune_best(const TuneEntry& e) {
+  int best = 0;
+  for (int k = 1; k < 3; ++k)
+    if (e.ms[k] < e.ms[best]) best = k;
+  return kGroupCand[best];
 }
 
 // Group count for a level: `fixed` when the caller set one, else the next
@@ -1160,14 +1169,12 @@ static int tune_pick(cur_ctx ctx, const int64_t key[6], int fixed, int* cand) {
   *cand = -1;
   if (fixed > 0) return fixed;
   TuneEntry* e = tune_find(ctx, key);
+  if (e->fixed > 0) return e->fixed;
   if (e->tried < 3) {
     *cand = e->tried;
     return kGroupCand[e->tried];
   }
-  int best = 0;
-  for (int k = 1; k < 3; ++k)
-    if (e->ms[k] < e->ms[best]) best = k;
-  return kGroupCand[best];
+  return tune_best(*e);
 }
 
 static void tune_record(cur_ctx ctx, const int64_t key[6], int cand, std::chrono::steady_clock::time_point t0) {

@@ -3,6 +3,7 @@
     python -m paper_2502_11017_amd.profsum stats   STATS_CSV [--top N] [--match TEXT]
     python -m paper_2502_11017_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
            --copy-bytes N --source FILE [--workload TEXT] [--command TEXT ...]
+           [--last N] [--bench-line FILE]
 
 ``stats`` prints the kernel table of a ``--kernel-trace --stats`` run
 (calls, total and average duration per kernel).
@@ -11,7 +12,10 @@
 HBM bytes per launch of one kernel and prints them as JSON.  Both counters
 are reported in KiB per dispatch; each is scaled by what it reads for the
 largest device copy in the same run (a plain copy of ``--copy-bytes`` read
-and written), so the figures are in bytes actually moved.
+and written), so the figures are in bytes actually moved.  With ``--last``
+only the final N dispatches count (the timed step of a bench run), and
+``--bench-line`` adds that run's algorithmic bytes per launch of the same
+launches for the ratio.
 """
 from __future__ import annotations
 
@@ -71,7 +75,7 @@ def _copy_scale(d, copy_bytes, what):
     return copy_bytes / (kib * 1024.0), kib
 
 
-def pass_traffic(fetch_csv, write_csv, kernel, copy_bytes):
+def pass_traffic(fetch_csv, write_csv, kernel, copy_bytes, last=0):
     f = _per_dispatch(fetch_csv)
     w = _per_dispatch(write_csv)
     fs, fkib = _copy_scale(f, copy_bytes, "FETCH_SIZE")
@@ -80,6 +84,8 @@ def pass_traffic(fetch_csv, write_csv, kernel, copy_bytes):
     wk = [v for _, (name, v) in sorted(w.items()) if kernel in name]
     if not fk or len(fk) != len(wk):
         raise SystemExit(f"{kernel}: {len(fk)} FETCH and {len(wk)} WRITE dispatches")
+    if last > 0:  # only the final `last` dispatches (the timed step of the run)
+        fk, wk = fk[-last:], wk[-last:]
     n = len(fk)
     fb = sum(fk) * 1024.0 * fs / n
     wb = sum(wk) * 1024.0 * ws / n
@@ -105,11 +111,20 @@ def main(argv=None):
     t.add_argument("--source", required=True)
     t.add_argument("--workload", default="")
     t.add_argument("--command", action="append", default=[])
+    t.add_argument("--last", type=int, default=0, help="average over the final N dispatches only")
+    t.add_argument("--bench-line", default=None,
+                   help="file holding the bench JSON line of the same run (its algorithmic bytes per launch)")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(kernel_stats(a.csv, a.top, a.match))
         return 0
-    rec = pass_traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
+    rec = pass_traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.last)
+    if a.bench_line:
+        with open(a.bench_line) as f:
+            line = [ln for ln in f if ln.startswith("{")][-1]
+        roof = json.loads(line)["roofline"]
+        rec["algorithmic_bytes_per_launch_same_launches"] = roof["algorithmic_bytes_per_launch"]
+        rec["traffic_over_algorithmic"] = rec["bytes_per_launch"] / roof["algorithmic_bytes_per_launch"]
     with open(a.source, "rb") as f:
         rec["source"] = os.path.relpath(a.source)
         rec["source_sha256_16"] = hashlib.sha256(f.read()).hexdigest()[:16]

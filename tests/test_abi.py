@@ -34,15 +34,15 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cur.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cur_opts), sizeof(cur_info),'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cur_opts), sizeof(cur_info),'
                    ' sizeof(cur_item), sizeof(cur_trace), offsetof(cur_opts, trace), offsetof(cur_item, I),'
-                   ' sizeof(cur_profile), offsetof(cur_opts, groups));}\n')
+                   ' sizeof(cur_profile), offsetof(cur_opts, groups), sizeof(cur_tune_entry));}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(cur.Opts), ctypes.sizeof(cur.Info), ctypes.sizeof(cur.Item),
             ctypes.sizeof(cur.Trace), cur.Opts.trace.offset, cur.Item.I.offset,
-            ctypes.sizeof(cur.Profile), cur.Opts.groups.offset]
+            ctypes.sizeof(cur.Profile), cur.Opts.groups.offset, ctypes.sizeof(cur.TuneEntry)]
     assert got == want
 
 
@@ -114,3 +114,11 @@ def test_strerror_covers_every_status():
     L = cur.lib()
     for s in (0, 1, -1, -2, -3, -4, -5, -6):
         assert L.cur_strerror(s).decode() != "unknown status"
+
+
+def test_tune_cache_argument_errors():
+    L = cur.lib()
+    n = ctypes.c_int32(0)
+    assert L.cur_tune_export(None, None, 0, ctypes.byref(n)) == cur.ERR_ARG
+    assert L.cur_tune_import(None, None, 0) == cur.ERR_ARG
+    assert L.cur_profile_enable(None, 1) == cur.ERR_ARG

@@ -289,3 +289,23 @@ def test_node_groups_do_not_change_the_selection(orc, dt):
     for (I1, J1, s1), (I3, J3, s3) in zip(outs1, outs3):
         assert s1 == s3
         assert torch.equal(I1, I3) and torch.equal(J1, J3)
+
+
+def test_tune_cache_round_trip():
+    """Three autotuned calls on one shape explore 1, 2 and 3 node groups; the
+    exported cache then names the fastest.  An imported choice is used as is
+    and the selection stays the same."""
+    say("case tune cache")
+    A = torch.from_numpy(W.gaussian(700, 1100, 22)).to(DEV)
+    ref = cur.select(A, 16, groups=1)
+    cur.tune_import([])
+    for _ in range(3):
+        cur.select(A, 16)
+    t = cur.tune_export()
+    assert t and all(e["tried"] == 3 and e["groups"] in (1, 2, 3) for e in t)
+    forced = [dict(e, groups=2) for e in t]
+    cur.tune_import(forced)
+    g = cur.select(A, 16)
+    assert torch.equal(g["I"], ref["I"]) and torch.equal(g["J"], ref["J"])
+    assert [e["groups"] for e in cur.tune_export()] == [2] * len(t)
+    cur.tune_import([])
