@@ -57,6 +57,14 @@ static cur_status check_matrix(cur_dtype dtype, const void* A, int64_t m, int64_
   return CUR_OK;
 }
 
+// The selection's row kernels address a column of the working matrices with a
+// 32-bit byte offset: one column must stay below 4 GiB.
+static cur_status check_select_rows(cur_dtype dtype, int64_t m) {
+  const int64_t es = dtype == CUR_F64 ? 8 : 4;
+  if (m * es >= ((int64_t)1 << 32)) return arg_error("m x element size must be below 4 GiB for selection");
+  return CUR_OK;
+}
+
 // Resolve the options (defaults filled in) or report an argument error.
 static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, int64_t n, cur_opts* out) {
   cur_opts o;
@@ -190,6 +198,8 @@ cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, in
                       int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info) {
   cur_status st = check_matrix(dtype, A, m, n, lda, r);
   if (st != CUR_OK) return st;
+  st = check_select_rows(dtype, m);
+  if (st != CUR_OK) return st;
   if (!I || !J) return arg_error("I and J must be non-NULL device pointers");
   cur_opts o;
   st = resolve_opts(opts, dtype, r, n, &o);
@@ -292,6 +302,7 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
   for (int32_t i = 0; i < count; ++i) {
     const cur_item& it = items[i];
     cur_status st = check_matrix((cur_dtype)it.dtype, it.A, it.m, it.n, it.lda, it.r);
+    if (st == CUR_OK) st = check_select_rows((cur_dtype)it.dtype, it.m);
     if (st != CUR_OK) return arg_error("item " + std::to_string(i) + ": " + last_error());
     if (!it.I || !it.J) return arg_error("item " + std::to_string(i) + ": I and J must be non-NULL");
     cur_opts o;

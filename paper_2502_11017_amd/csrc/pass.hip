@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "cur_device.hpp"
 #include "cur_internal.hpp"
@@ -16,22 +17,126 @@ namespace cur {
 
 constexpr int kPassWaves = 6;  // wavefronts per SIMD the pass is compiled for
 
+// |x| as an unsigned integer of the element's width: for |x| >= 0 the bit
+// pattern orders like the value, so a lane compares candidates with one
+// integer compare in the input type (no conversion to FP64 per element).
+template <typename T>
+struct AbsBits;
+template <>
+struct AbsBits<double> {
+  using U = uint64_t;
+  static __device__ __forceinline__ U of(double x) {
+    return (U)__double_as_longlong(x) & 0x7fffffffffffffffull;
+  }
+};
+template <>
+struct AbsBits<float> {
+  using U = uint32_t;
+  static __device__ __forceinline__ U of(float x) { return (U)__float_as_uint(x) & 0x7fffffffu; }
+};
+
 // Best candidate of one row scanned in ascending column order (key row * r + c):
-// the first strictly larger |x| wins, NaN never does.  Compares the bit
-// pattern of |x|, which orders like the value for |x| >= 0.
+// the first strictly larger |x| wins, NaN never does.
+template <typename T>
 struct RowBest {
-  uint64_t bits = 0;
-  double x = 0.0;
+  typename AbsBits<T>::U bits = 0;
+  T x = (T)0;
   int c = -1;
-  __device__ __forceinline__ void take(double v, int col) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
+  __device__ __forceinline__ void take(T v, int col) {
+    const typename AbsBits<T>::U u = AbsBits<T>::of(v);
     if (v == v && (c < 0 || u > bits)) {
       bits = u;
       x = v;
       c = col;
     }
   }
+  // the row's candidate in the tile-argmax order
+  __device__ __forceinline__ void to_cand(Cand& best, int64_t row, int r) const {
+    if (c >= 0) {
+      best.val = fabs((double)x);
+      best.sval = (double)x;
+      best.key = row * r + c;
+      best.row = row;
+      best.pos = c;
+    }
+  }
 };
+
+// Best candidate of one row in an ACA step: larger |x| first, ties to the
+// smaller original column id (the key row * nc + id), NaN never.  Same order
+// as the tile argmax restricted to one row.
+template <typename T>
+struct AcaBest {
+  typename AbsBits<T>::U bits = 0;
+  T x = (T)0;
+  int id = 0x7fffffff;
+  int pos = -1;
+  __device__ __forceinline__ void take(T v, int cid, int p) {
+    const typename AbsBits<T>::U u = AbsBits<T>::of(v);
+    if (v == v && (pos < 0 || u > bits || (u == bits && cid < id))) {
+      bits = u;
+      x = v;
+      id = cid;
+      pos = p;
+    }
+  }
+  __device__ __forceinline__ void to_cand(Cand& best, int64_t row, int nc) const {
+    if (pos >= 0) {
+      best.val = fabs((double)x);
+      best.sval = (double)x;
+      best.key = row * nc + id;
+      best.row = row;
+      best.pos = pos;
+    }
+  }
+};
+
+// Global-address-space view of a device pointer: the streaming kernels'
+// loads and stores become global_* instructions, whose completion counts
+// apart from LDS and scalar loads, so a wait for one does not drain the other.
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T*;
+
+// Element at byte offset `off` of a column whose base is wavefront-uniform:
+// a scalar base plus one 32-bit offset register per lane, shared by every
+// load and store of the row (the selection checks m * sizeof(T) < 2^32).
+template <typename T>
+__device__ __forceinline__ T col_ld(GPtr<const T> col, uint32_t off) {
+  return *(GPtr<const T>)((__attribute__((address_space(1))) const char*)col + off);
+}
+template <typename T>
+__device__ __forceinline__ void col_st(GPtr<T> col, uint32_t off, T v) {
+  *(GPtr<T>)((__attribute__((address_space(1))) char*)col + off) = v;
+}
+
+// Per-column values of a pass (up to 256 columns) held one per lane: column
+// c in lane c & 63 of register c >> 6, read back with readlane.  Loaded once
+// per workgroup with coalesced loads, they cost no memory access between a
+// round's loads and its stores.
+constexpr int kLaneCols = 256;
+template <typename V>
+__device__ __forceinline__ void lane_load(V (&reg)[4], const V* src_generic, int n) {
+  const int lane = threadIdx.x & 63;
+  const GPtr<const V> src = (GPtr<const V>)src_generic;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {  // n >= 1: clamped loads, then a select (no branch per load)
+    const int c = lane + 64 * q;
+    const V v = src[min(c, n - 1)];
+    reg[q] = c < n ? v : (V)0;
+  }
+}
+// reg[q] for a wavefront-uniform q < 4, as a select tree (stays in registers)
+template <typename V>
+__device__ __forceinline__ V lane_reg(const V (&reg)[4], int q) {
+  const V lo = (q & 1) ? reg[1] : reg[0];
+  const V hi = (q & 1) ? reg[3] : reg[2];
+  return (q & 2) ? hi : lo;
+}
+__device__ __forceinline__ double lane_read(double v, int l) { return readlane_f64(v, l); }
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 // Tile epilogue of both row kernels: block argmax, the tile winner to the
 // node's partial array, and (when profiling) the node's algorithmic bytes,
@@ -52,8 +157,8 @@ __device__ __forceinline__ void pass_finish(Node& nd, int tile, Cand best, Cand*
   }
 }
 
-// ACA step, fresh B, or row swap over one tile of kTileRows rows, fused with
-// the tile's argmax; the tile winner goes to the node's partial array.
+// ACA step or row swap over one tile of kTileRows rows, fused with the
+// tile's argmax; the tile winner goes to the node's partial array.
 template <typename T, int RMAX>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPassWaves)))
 void k_pass(Node* nodes, unsigned long long* prof) {
@@ -68,113 +173,172 @@ void k_pass(Node* nodes, unsigned long long* prof) {
   const int64_t row0 = (int64_t)tile * kTileRows;
   const int64_t row = row0 + tid;
   const bool valid = row < m;
-  T* W = (T*)nd.work;
-  const T* P = (const T*)nd.panel;
+  const GPtr<T> W = (GPtr<T>)nd.work;
+  const GPtr<const T> P = (GPtr<const T>)nd.panel;
+  // element (row, c) of a column-major working matrix: the column's base
+  // (wavefront-uniform) plus the row's byte offset.  Rows past m load row
+  // m - 1 and store nothing: the rounds run with every lane active, because
+  // the per-column values below are read across lanes (readlane), which needs
+  // them computed in all lanes.
+  const uint32_t ro = (uint32_t)(valid ? row : m - 1) * (uint32_t)sizeof(T);
 
   __shared__ Cand sc[kThreads / 64];
 
   Cand best = cand_none();
   // Columns per register round: every load of a round is issued before the
   // round's first store (the stores go to the array the loads read, which the
-  // compiler cannot reorder across).  64 bytes per lane per round keeps the
+  // compiler cannot reorder across).  16 columns per round keeps the
   // register count low enough for kPassWaves wavefronts per SIMD: a launch is
   // thousands of short workgroups, each a chain of dependent latencies (node
   // fields, data, block argmax), so residency, not per-wavefront depth, sets
-  // the pass time.
-  constexpr int NR = 64 / (int)sizeof(T);
+  // the pass time.  A round never crosses a multiple of 64 columns, so its
+  // per-column values sit in one lane register.
+  constexpr int NR = 16;
+  static_assert(64 % NR == 0, "rounds must not straddle lane registers");
+  using BT = std::integral_constant<bool, true>;
+  using BF = std::integral_constant<bool, false>;
 
   if (st == ST_ACA) {
     const int t = nd.t, na = nd.na, nc = nd.nc;
     const int32_t* cmap = nd.colmap;
-    const T* src = (t <= 1) ? P : W;
+    const double* f = nd.vec;
+    const GPtr<const T> src = (t <= 1) ? P : (GPtr<const T>)W;
+    const bool in_lanes = na <= kLaneCols;
+    int idr[4];
+    T fr[4];
+    if (in_lanes) {
+      lane_load(idr, cmap, na);
+      if (t > 0) {
+        double fd[4];
+        lane_load(fd, f, na);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fr[q] = (T)fd[q];
+      }
+    }
+    AcaBest<T> ab;
     if (t == 0) {
-      if (valid)
+      // first step: the argmax of the panel itself
+      auto rounds = [&](auto lanes) {
         for (int c0 = 0; c0 < na; c0 += NR) {
           T xs[NR];
 #pragma unroll
-          for (int u = 0; u < NR; ++u) xs[u] = (c0 + u < na) ? src[(int64_t)(c0 + u) * m + row] : (T)0;
+          for (int u = 0; u < NR; ++u) {
+            const int cc = min(c0 + u, na - 1);  // in range; extra lanes of the round are ignored
+            xs[u] = col_ld<T>(src + (int64_t)cc * m, ro);
+          }
+          int idq = 0;
+          if constexpr (decltype(lanes)::value) idq = lane_reg(idr, c0 >> 6);
 #pragma unroll
           for (int u = 0; u < NR; ++u) {
             const int c = c0 + u;
-            if (c >= na) break;
-            Cand o;
-            o.val = fabs((double)xs[u]);
-            o.sval = (double)xs[u];
-            o.key = row * nc + cmap[c];
-            o.row = row;
-            o.pos = c;
-            cand_take(best, o);
+            if (c < na) {
+              int idu;
+              if constexpr (decltype(lanes)::value) idu = lane_read(idq, c & 63);
+              else idu = cmap[c];
+              if (valid) ab.take(xs[u], idu, c);
+            }
           }
         }
+      };
+      if (in_lanes) rounds(BT());
+      else rounds(BF());
     } else {
       // R <- R - R(:, pc) f^T with row pi zeroed; the last active column moves
       // into the freed slot pc.  A later round only reads columns past the
       // earlier ones and writes those columns or pc, which was read already.
       const int pc = nd.pend_k;
       const int64_t pi = nd.pend_i;
-      const double* f = nd.vec;
-      if (valid) {
-        const T g = src[(int64_t)pc * m + row];
+      auto rounds = [&](auto lanes) {
+        const T g = col_ld<T>(src + (int64_t)pc * m, ro);
         for (int c0 = 0; c0 < na; c0 += NR) {
           T xs[NR];
 #pragma unroll
-          for (int u = 0; u < NR; ++u) xs[u] = (c0 + u < na) ? src[(int64_t)(c0 + u) * m + row] : (T)0;
+          for (int u = 0; u < NR; ++u) {
+            const int cc = min(c0 + u, na - 1);
+            xs[u] = col_ld<T>(src + (int64_t)cc * m, ro);
+          }
+          T fq = (T)0;
+          int idq = 0;
+          if constexpr (decltype(lanes)::value) {
+            fq = lane_reg(fr, c0 >> 6);
+            idq = lane_reg(idr, c0 >> 6);
+          }
 #pragma unroll
           for (int u = 0; u < NR; ++u) {
             const int c = c0 + u;
-            if (c >= na) break;
-            if (c == pc) continue;
-            T x = fma_t<T>(-g, (T)f[c], xs[u]);
-            if (row == pi) x = (T)0;
-            const int np = (c == na - 1) ? pc : c;
-            W[(int64_t)np * m + row] = x;
-            Cand o;
-            o.val = fabs((double)x);
-            o.sval = (double)x;
-            o.key = row * nc + cmap[c];
-            o.row = row;
-            o.pos = np;
-            cand_take(best, o);
+            if (c < na && c != pc) {
+              // more than kLaneCols columns (a leaf block wider than 256): the
+              // coefficients are read here, after the previous stores (slower)
+              T fcu;
+              int idu;
+              if constexpr (decltype(lanes)::value) {
+                fcu = lane_read(fq, c & 63);
+                idu = lane_read(idq, c & 63);
+              } else {
+                fcu = (T)f[c];
+                idu = cmap[c];
+              }
+              T x = fma_t<T>(-g, fcu, xs[u]);
+              if (row == pi) x = (T)0;
+              const int np = (c == na - 1) ? pc : c;
+              if (valid) {
+                col_st<T>(W + (int64_t)np * m, ro, x);
+                ab.take(x, idu, np);
+              }
+            }
           }
         }
-      }
+      };
+      if (in_lanes) rounds(BT());
+      else rounds(BF());
     }
+    ab.to_cand(best, row, nc);
   } else {
-    // No mask of the selected rows here: a selected row is exactly e_k, the
-    // update keeps it so (its entry in column ks is 0, and fma(-0, v, x) = x),
-    // and |e_k| <= 1 < 1 + tau, so such a row can win a tile only when no
-    // row swap is due, where the winner's identity is not used.
-    RowBest rb;
+    // B <- B - B(:, ks) v^T, row is set to e_ks^T.  No mask of the selected
+    // rows here: a selected row is exactly e_k, the update keeps it so (its
+    // entry in column ks is 0, and fma(-0, v, x) = x), and |e_k| <= 1 < 1 + tau,
+    // so such a row can win a tile only when no row swap is due, where the
+    // winner's identity is not used.
+    const int ks = nd.pend_k;
+    const int64_t is = nd.pend_i;
+    T vr[4];
     {
-      // B <- B - B(:, ks) v^T, row is set to e_ks^T
-      const int ks = nd.pend_k;
-      const int64_t is = nd.pend_i;
-      const double* v = nd.vec;
-      if (valid) {
-        const T g = W[(int64_t)ks * m + row];
-        for (int c0 = 0; c0 < r; c0 += NR) {
-          T bs[NR];
+      double vd[4];
+      lane_load(vd, nd.vec, r);  // r <= 128 < kLaneCols
 #pragma unroll
-          for (int u = 0; u < NR; ++u) bs[u] = (c0 + u < r) ? W[(int64_t)(c0 + u) * m + row] : (T)0;
+      for (int q = 0; q < 4; ++q) vr[q] = (T)vd[q];
+    }
+    RowBest<T> rb;
+    {
+      const T g = col_ld<T>(W + (int64_t)ks * m, ro);
+      // all rounds unrolled (r <= RMAX): no loop header at which the compiler
+      // would wait for every outstanding load
 #pragma unroll
-          for (int u = 0; u < NR; ++u) {
-            const int c = c0 + u;
-            if (c >= r) break;
-            T b = fma_t<T>(-g, (T)v[c], bs[u]);
+      for (int q = 0; q < (RMAX + NR - 1) / NR; ++q) {
+        const int c0 = q * NR;
+        if (c0 >= r) break;
+        T bs[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+          const int cc = min(c0 + u, r - 1);  // in range; extra lanes of the round are ignored
+          bs[u] = col_ld<T>(W + (int64_t)cc * m, ro);
+        }
+        const T vq = lane_reg(vr, c0 >> 6);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+          const int c = c0 + u;
+          if (c < r) {
+            T b = fma_t<T>(-g, lane_read(vq, c & 63), bs[u]);
             if (row == is) b = (c == ks) ? (T)1 : (T)0;
-            W[(int64_t)c * m + row] = b;
-            rb.take((double)b, c);
+            if (valid) {
+              col_st<T>(W + (int64_t)c * m, ro, b);
+              rb.take(b, c);
+            }
           }
         }
       }
     }
-    if (rb.c >= 0) {
-      best.val = fabs(rb.x);
-      best.sval = rb.x;
-      best.key = row * r + rb.c;
-      best.row = row;
-      best.pos = rb.c;
-    }
+    rb.to_cand(best, row, r);
   }
 
   int64_t cols;  // algorithmic columns: working columns read + columns written
@@ -219,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   }
   __syncthreads();
   const int slot = sslot[tid];
-  RowBest rb;
+  RowBest<T> rb;
   for (int c0 = 0; c0 < r; c0 += CB) {
     const int nb = min(CB, r - c0);
     __syncthreads();
@@ -252,19 +416,13 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
           T b = (T)acc[j];
           if (slot >= 0) b = (c == slot) ? (T)1 : (T)0;
           W[(int64_t)c * m + row] = b;
-          if (slot < 0) rb.take((double)b, c);
+          if (slot < 0) rb.take(b, c);
         }
       }
     }
   }
   Cand best = cand_none();
-  if (rb.c >= 0) {
-    best.val = fabs(rb.x);
-    best.sval = rb.x;
-    best.key = row * r + rb.c;
-    best.row = row;
-    best.pos = rb.c;
-  }
+  rb.to_cand(best, row, r);
   pass_finish(nd, tile, best, sc, prof, m * 2 * (int64_t)r * (int64_t)sizeof(T));
 }
 

@@ -58,6 +58,7 @@ def _sel(m=10, n=12, lda=12, r=3, A=1, I=1, J=1, opts=None, dtype=cur.F64):
     (dict(r=0), "r must"), (dict(r=11), "r must"), (dict(m=0), "m and n"), (dict(lda=5), "lda"),
     (dict(A=0), "A is NULL"), (dict(I=0), "I and J"), (dict(dtype=7), "dtype"),
     (dict(r=200, m=300, n=300, lda=300), "r > 128"),
+    (dict(m=1 << 29, n=64, lda=64), "4 GiB"), (dict(m=1 << 30, n=64, lda=64, dtype=cur.F32), "4 GiB"),
 ])
 def test_select_argument_errors_on_host(kw, msg):
     assert _sel(**kw) == cur.ERR_ARG
