@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_split_cols_fp8(const float* __rest
 // cover the other's staging and epilogue.  Rows or columns beyond m, n are
 // zero operands and are skipped in the epilogue.
 // part[3*block] = {max|E|, sum E^2, sum A^2}.
-constexpr int kMK = 64;  // k values per staged chunk
+constexpr int kMK = 32;  // k values per staged chunk
 
 template <int PREC>
 struct MpLds {
@@ -147,6 +147,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mp(const float* __restric
       acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
       acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+  // The tile of A (the only operand streamed from HBM) is requested first,
+  // so its latency overlaps the products; rows/columns past the matrix load
+  // a clamped in-range element and are skipped in the epilogue.  The FP8
+  // form holds a second accumulator set, so it requests the first PF of its
+  // four 16-row groups here and the rest at the start of the epilogue.
+  constexpr int PF = PREC == CUR_PREC_FP8 ? 2 : 4;
+  float av[4][4][4];
+  auto load_a = [&](int i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = min(rb0 + wr + 16 * i + 4 * lk + v, m - 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = min(cb0 + wc + 16 * j + lr, n - 1);
+        av[i][v][j] = A[row * lda + col];
+      }
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < PF; ++i) load_a(i);
   for (int k0 = 0; k0 < rp; k0 += kMK) {
     // stage: 4 operand terms x 128 strips x (kMK * ES) bytes as 16-byte pieces
     constexpr int PIECES = kMK * ES / 16;  // per strip
@@ -213,6 +233,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mp(const float* __restric
       }
     }
   }
+#pragma unroll
+  for (int i = PF; i < 4; ++i) load_a(i);
   double emax = 0.0, esq = 0.0, asq = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -227,11 +249,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mp(const float* __restric
         if (col >= n) continue;
         float p = acc[i][j][v];
         if constexpr (PREC == CUR_PREC_FP8) p = sa * bs[col] * (p + 0.0625f * acc2[i][j][v]);
-        const double av = (double)A[row * lda + col];
-        const double e = av - (double)p;
+        const double a = (double)av[i][v][j];
+        const double e = a - (double)p;
         emax = fmax(emax, fabs(e));
         esq = fma(e, e, esq);
-        asq = fma(av, av, asq);
+        asq = fma(a, a, asq);
       }
     }
 #pragma unroll
