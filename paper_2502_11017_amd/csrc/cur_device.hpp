@@ -192,14 +192,16 @@ __device__ void block_lu_inverse(const double* LU, const int* perm, int r, doubl
 
 // ---------------------------------------------------------------- register LU (r <= 64)
 // LU with partial pivoting and G^{-1} for r <= RMAX <= 64, held in registers:
-// lane p owns row p of G (physical order, never moved), wavefront w owns the
-// columns c = w + 4 j.  Row exchanges are tracked as positions instead of data
-// moves.  Every value that reaches U, X or the volume is computed with the
-// operands and in the order of block_gepp followed by block_lu_inverse, so the
-// results are identical bit for bit:
+// lane p owns row p of G (physical order, never moved).  Columns come in
+// blocks of 8 dealt round-robin to the 4 wavefronts: column c is in
+// wavefront (c / 8) & 3 at local index lu_j(c).  Row exchanges are tracked as
+// positions instead of data moves.  Every value that reaches U, X or the
+// volume is computed with the operands and in the order of block_gepp
+// followed by block_lu_inverse, so the results are identical bit for bit:
 //   * the pivot of step k is the largest |G(p,k)| over unpivoted rows, ties to
 //     the smallest position; multipliers l_p = G(p,k) / d;
-//   * G(p,c) = fma(-l_p, G(P,c), G(p,c)) for c > k on unpivoted rows p;
+//   * G(p,c) = fma(-l_p, G(P,c), G(p,c)) on unpivoted rows p, steps in
+//     ascending order for every element;
 //   * the forward substitution L y = P e_c rides along as an augmented right
 //     side Y (starting from the identity in physical order), updated with the
 //     same multipliers: row p receives fma(-L(i,k), y_k, .) for k ascending;
@@ -210,25 +212,32 @@ __device__ void block_lu_inverse(const double* LU, const int* perm, int r, doubl
 // unpivoted rows without testing c > k: the L part is left as scratch.  In Y,
 // row P is exactly +0 in every column c whose row c is not yet pivoted, and an
 // fma with a +0 product leaves a target that is never -0 unchanged.
-// The wavefront owning column k+1 updates that column first, chooses its
-// pivot and publishes it before its bulk update, so a step needs one block
-// barrier.  The pivot row of a wavefront's columns is broadcast through LDS.
+// Blocked schedule: the wavefront owning the 8 columns of panel b factors
+// them alone (pivot search, multipliers, updates inside the panel; the pivot
+// row's values come from its own lanes by readlane) and publishes the 8
+// steps' multipliers and pivots through LDS; after one block barrier every
+// wavefront replays those steps on its other columns.  Each element still
+// receives its updates one step at a time in ascending order, so the
+// arithmetic is that of the unblocked elimination; a barrier is paid per 8
+// steps instead of per step.
 struct LuScratch {
-  double l[2][64];        // multipliers of the pending step (double-buffered)
-  int info[2];            // pivot row | position << 8 | singular << 16
-  double diag[64];        // U(k,k) in step order
-  int perm[64];           // physical row at position k
-  double xb[4][16];       // per-wavefront staging of one row of X
-  double prow[4][2][16];  // per-wavefront copy of the pivot row (G part, Y part)
+  double pl[2][8][64];  // multipliers of a panel's steps (double-buffered by panel)
+  int pinfo[2][8];      // per step: pivot row | position << 8 | singular << 16
+  double diag[64];      // U(k,k) in step order
+  int perm[64];         // physical row at position k
+  double xb[4][16];     // per-wavefront staging of one row of X
 };
 template <int RMAX>
 struct LuRegs {
   static_assert(RMAX == 32 || RMAX == 64, "register LU covers r <= 64");
   static constexpr int NJ = RMAX / 4;
-  double g[NJ];  // G / LU, columns w + 4 j of row `lane`
+  double g[NJ];  // G / LU, this wavefront's columns of row `lane`
   double y[NJ];  // augmented right side, same columns
   int pos;       // position of this lane's row
 };
+
+// Column of local index j in wavefront w (8-column blocks dealt round-robin).
+__device__ __forceinline__ int lu_col(int w, int j) { return ((((j >> 3) << 2) + w) << 3) + (j & 7); }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -267,40 +276,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Pivot of column k chosen by the wavefront that owns it: v = this lane's
-// entry, cand = row not yet pivoted.  Largest |v| first (for |v| >= 0 the bit
-// pattern orders like the value; NaN is no candidate), ties to the smallest
-// position.  Publishes multipliers and pivot to S.
-__device__ __forceinline__ void wave_pivot(double v, bool cand, int pos, int k, int buf, LuScratch& S) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t key = (cand && v == v) ? (uint64_t)__double_as_longlong(fabs(v)) : 0ull;
-  const uint64_t best = wave_max_u64(key);
-  uint64_t tied = __ballot(key == best);
-  int P = (int)__builtin_ctzll(tied);
-  if (tied & (tied - 1)) {  // equal magnitudes: smallest position
-    int bp = 0x7fffffff;
-    while (tied) {
-      const int b = (int)__builtin_ctzll(tied);
-      const int pb = __builtin_amdgcn_readlane(pos, b);
-      if (pb < bp) {
-        bp = pb;
-        P = b;
-      }
-      tied &= tied - 1;
-    }
-  }
-  P = __builtin_amdgcn_readfirstlane(P);
-  const int pp = __builtin_amdgcn_readlane(pos, P);
-  const double d = readlane_f64(v, P);
-  const bool bad = best == 0ull;
-  S.l[buf][lane] = (cand && lane != P && !bad) ? v / d : 0.0;
-  if (lane == 0) {
-    S.info[buf] = P | (pp << 8) | ((bad ? 1 : 0) << 16);
-    S.diag[k] = d;
-    S.perm[k] = P;
-  }
-}
-
 // a[j] for a wavefront-uniform j < NJ (a power of two): a tree of selects on
 // the bits of j, which keeps the array in registers.
 template <int NJ>
@@ -325,71 +300,113 @@ __device__ __forceinline__ double reg_pick(const double (&a)[NJ], int j) {
 template <int RMAX, class LoadG>
 __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, double* LUl, LuScratch& S) {
   constexpr int NJ = LuRegs<RMAX>::NJ;
+  constexpr int NB = NJ / 8;  // column blocks per wavefront
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool live = lane < r;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    const int c = w + 4 * j;
+    const int c = lu_col(w, j);
     R.g[j] = (live && c < r) ? ldg(lane, c) : 0.0;
     R.y[j] = (lane == c) ? 1.0 : 0.0;
   }
   R.pos = lane;
   bool done = !live;
-  if (w == 0) wave_pivot(R.g[0], live, lane, 0, 0, S);
-  double* pr = S.prow[w][0];
-  double* pyr = S.prow[w][1];
-  for (int k = 0; k < r; ++k) {
-    const int k1 = k + 1;
-    const bool owner = k1 < r && w == (k1 & 3);
-    double cv = 0.0;
-    if (owner) cv = reg_pick<NJ>(R.g, k1 >> 2);  // column k+1 before this step
+  const int npanels = (r + 7) >> 3;
+  for (int b = 0; b < npanels; ++b) {
+    const int buf = b & 1;
+    const int k0 = b << 3;
+    const int ns = min(8, r - k0);
+    const int owner = b & 3, lbo = b >> 2;  // owning wavefront, its local block
+    bool rdone = done;  // "pivoted" as of the step being replayed below
+    if (w == owner) {
+#pragma unroll
+      for (int lb = 0; lb < NB; ++lb) {
+        if (lb != lbo) continue;
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+          if (st >= ns) break;
+          const int k = k0 + st;
+          const double v = R.g[lb * 8 + st];
+          // pivot: largest |v| over unpivoted rows (bit pattern of |v| orders
+          // like the value; NaN is no candidate), ties to the smallest position
+          const uint64_t key = (!done && v == v) ? (uint64_t)__double_as_longlong(fabs(v)) : 0ull;
+          const uint64_t best = wave_max_u64(key);
+          uint64_t tied = __ballot(key == best);
+          int P = (int)__builtin_ctzll(tied);
+          if (tied & (tied - 1)) {
+            int bp = 0x7fffffff;
+            while (tied) {
+              const int q = (int)__builtin_ctzll(tied);
+              const int pq = __builtin_amdgcn_readlane(R.pos, q);
+              if (pq < bp) {
+                bp = pq;
+                P = q;
+              }
+              tied &= tied - 1;
+            }
+          }
+          P = __builtin_amdgcn_readfirstlane(P);
+          const int pp = __builtin_amdgcn_readlane(R.pos, P);
+          const double d = readlane_f64(v, P);
+          const bool bad = best == 0ull;
+          const bool upd = !done && lane != P && !bad;
+          const double l = upd ? v / d : 0.0;
+          S.pl[buf][st][lane] = l;
+          if (lane == 0) {
+            S.pinfo[buf][st] = P | (pp << 8) | ((bad ? 1 : 0) << 16);
+            S.diag[k] = d;
+            S.perm[k] = P;
+          }
+          if (bad) break;
+          // the rest of the panel (columns k+1 .. of this block)
+#pragma unroll
+          for (int t = st + 1; t < 8; ++t) R.g[lb * 8 + t] = fma(-l, readlane_f64(R.g[lb * 8 + t], P), R.g[lb * 8 + t]);
+          if (lane == P) {
+            done = true;
+            R.pos = k;
+          } else if (!done && R.pos == k) {
+            R.pos = pp;
+          }
+        }
+      }
+    }
     __syncthreads();
-    const int buf = k & 1;
-    const int info = __builtin_amdgcn_readfirstlane(S.info[buf]);
-    if (info >> 16) return false;
-    const int P = info & 0xff, pp = (info >> 8) & 0xff;
-    const double l = S.l[buf][lane];
-    const bool upd = !done && lane != P;
-    if (lane == P) {
-      done = true;
-      R.pos = k;
-    } else if (!done && R.pos == k) {
-      R.pos = pp;
-    }
-    if (owner) {
-      const double pc = readlane_f64(cv, P);
-      if (upd) cv = fma(-l, pc, cv);
-      wave_pivot(cv, !done, R.pos, k1, buf ^ 1, S);
-    }
-    // bulk update of this wavefront's columns
-    if (lane == P) {
+    // replay the panel's steps on this wavefront's other columns and on Y
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      if (st >= ns) break;
+      const int k = k0 + st;
+      const int info = __builtin_amdgcn_readfirstlane(S.pinfo[buf][st]);
+      if (info >> 16) return false;
+      const int P = info & 0xff, pp = (info >> 8) & 0xff;
+      const bool mine = w == owner;  // the owner's lanes already took this step's bookkeeping
+      // the published multiplier is 0 for the pivot row and the rows pivoted
+      // before, and fma(-0, u, g) is g (up to the sign of a zero g, which no
+      // comparison, pivot or result value sees), so the update needs no select
+      const double l = S.pl[buf][st][lane];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        pr[j] = R.g[j];
-        pyr[j] = R.y[j];
+        if (mine && (j >> 3) == lbo) continue;  // the panel itself
+        R.g[j] = fma(-l, readlane_f64(R.g[j], P), R.g[j]);
       }
-    }
-    wave_lds_sync();
-    double pg[NJ], py[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      pg[j] = pr[j];
-      py[j] = pyr[j];
-    }
-    if (upd) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        R.g[j] = fma(-l, pg[j], R.g[j]);
-        R.y[j] = fma(-l, py[j], R.y[j]);
+      for (int j = 0; j < NJ; ++j) R.y[j] = fma(-l, readlane_f64(R.y[j], P), R.y[j]);
+      if (!mine) {
+        if (lane == P) {
+          R.pos = k;
+        } else if (!rdone && R.pos == k) {
+          R.pos = pp;
+        }
       }
+      if (lane == P) rdone = true;
     }
-    wave_lds_sync();
+    done = rdone;
   }
   if (live) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int c = w + 4 * j;
+      const int c = lu_col(w, j);
       if (c < r) LUl[c * RMAX + lane] = R.g[j];
     }
   }
@@ -411,7 +428,7 @@ __device__ __forceinline__ void lu_back_reg(int r, LuRegs<RMAX>& R, const double
   const int permv = lane < r ? S.perm[lane] : 0;
   const double diagv = lane < r ? S.diag[lane] : 1.0;
   double* xb = S.xb[w];
-  const int cl = w + 4 * lane;  // the column this lane divides
+  const int cl = lu_col(w, lane);  // the column this lane divides (lanes < NJ)
   double u = lane < r ? LUl[(r - 1) * RMAX + lane] : 0.0;  // U(pos, k) of this lane's row
   for (int k = r - 1; k >= 0; --k) {
     const int Pk = __builtin_amdgcn_readlane(permv, k);
