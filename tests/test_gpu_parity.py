@@ -67,6 +67,7 @@ CASES_F64 = [
     (777, 129, 1, 0, 6),       # r = 1
     (260, 2048, 32, 32, 7),    # 64 leaves
     (2000, 640, 96, 128, 8),   # r in the 128 bucket
+    (600, 1100, 16, 300, 9),   # leaf blocks wider than 256 columns (300, 300, 500)
 ]
 
 
@@ -153,7 +154,7 @@ def test_select_errors():
     assert ei.value.status == cur.ERR_ARG
 
 
-@pytest.mark.parametrize("m,n,r,w,seed", [(400, 600, 12, 32, 11), (1500, 900, 40, 64, 12)])
+@pytest.mark.parametrize("m,n,r,w,seed", [(400, 600, 12, 32, 11), (1500, 900, 40, 64, 12), (700, 1000, 20, 300, 13)])
 def test_select_f32_volume_ratio(orc, m, n, r, w, seed):
     A64 = W.c2(seed, n=max(m, n))[:m, :n].contiguous()
     A = A64.to(torch.float32).to(DEV)
