@@ -221,8 +221,8 @@ __device__ void block_lu_inverse(const double* LU, const int* perm, int r, doubl
 // arithmetic is that of the unblocked elimination; a barrier is paid per 8
 // steps instead of per step.
 struct LuScratch {
-  double pl[2][8][64];  // multipliers of a panel's steps (double-buffered by panel)
-  int pinfo[2][8];      // per step: pivot row | position << 8 | singular << 16
+  double pl[3][8][64];  // multipliers of a panel's steps (three panels in flight)
+  int pinfo[3][8];      // per step: pivot row | position << 8 | singular << 16
   double diag[64];      // U(k,k) in step order
   int perm[64];         // physical row at position k
   double xb[4][16];     // per-wavefront staging of one row of X
@@ -270,6 +270,27 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return max(max(readlane_u64(v, 0), readlane_u64(v, 16)), max(readlane_u64(v, 32), readlane_u64(v, 48)));
 }
 
+// Largest 32-bit unsigned value over the wavefront, returned uniformly (same
+// exchanges as wave_max_u64 on one word).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, true));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, true));
+  const uint32_t a = max((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
+  const uint32_t b = max((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+  return max(a, b);
+}
+
+// The same maximum for 64-bit values as two 32-bit passes: the high words,
+// then the low words of the lanes whose high word is the maximum.
+__device__ __forceinline__ uint64_t wave_max_u64_split(uint64_t v) {
+  const uint32_t hi = (uint32_t)(v >> 32);
+  const uint32_t mh = wave_max_u32(hi);
+  const uint32_t ml = wave_max_u32(hi == mh ? (uint32_t)v : 0u);
+  return ((uint64_t)mh << 32) | ml;
+}
+
 // Order the LDS accesses of one wavefront's lanes around a hand-off.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -313,16 +334,58 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
   R.pos = lane;
   bool done = !live;
   const int npanels = (r + 7) >> 3;
+  // One step of a published panel on column set `cols` of this wavefront:
+  // 0 all G columns except local block `skip`, plus Y; 1 only local block
+  // `only` of G.  The published multiplier is 0 for the pivot row and the rows
+  // pivoted before, and fma(-0, u, g) is g (up to the sign of a zero g, which
+  // no comparison, pivot or result value sees), so no select is needed.
+  auto replay = [&](int pb, int which, int blk) {
+    const int pbuf = pb % 3;
+    const int pns = min(8, r - (pb << 3));
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      if (st >= pns) break;
+      const int P = __builtin_amdgcn_readfirstlane(S.pinfo[pbuf][st]) & 0xff;
+      const double l = S.pl[pbuf][st][lane];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (which == 0 && (j >> 3) == blk) continue;
+        if (which == 1 && (j >> 3) != blk) continue;
+        R.g[j] = fma(-l, readlane_f64(R.g[j], P), R.g[j]);
+      }
+      if (which == 0) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) R.y[j] = fma(-l, readlane_f64(R.y[j], P), R.y[j]);
+      }
+    }
+  };
+  // Schedule per panel b (owner b & 3):
+  //   owner:       factors b (its block lb = b >> 2 is up to date), publishes;
+  //   barrier;
+  //   every wave:  takes the position bookkeeping of b's steps (the owner did);
+  //   next owner:  replays b on its block of panel b + 1 only (the critical
+  //                path), and owes b on everything else;
+  //   the others:  pay what they owe (the previous panel, on all but the block
+  //                they factored), then replay b on all their columns (the
+  //                owner: all but its panel).
+  // Every element still receives the steps in ascending order.
+  int owe = -1, owe_skip = -1;
   for (int b = 0; b < npanels; ++b) {
-    const int buf = b & 1;
+    const int buf = b % 3;
     const int k0 = b << 3;
     const int ns = min(8, r - k0);
     const int owner = b & 3, lbo = b >> 2;  // owning wavefront, its local block
-    bool rdone = done;  // "pivoted" as of the step being replayed below
     if (w == owner) {
 #pragma unroll
       for (int lb = 0; lb < NB; ++lb) {
         if (lb != lbo) continue;
+        int pinf[8];
+        double dg[8];
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+          pinf[st] = 1 << 16;
+          dg[st] = 0.0;
+        }
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
           if (st >= ns) break;
@@ -331,7 +394,7 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
           // pivot: largest |v| over unpivoted rows (bit pattern of |v| orders
           // like the value; NaN is no candidate), ties to the smallest position
           const uint64_t key = (!done && v == v) ? (uint64_t)__double_as_longlong(fabs(v)) : 0ull;
-          const uint64_t best = wave_max_u64(key);
+          const uint64_t best = wave_max_u64_split(key);
           uint64_t tied = __ballot(key == best);
           int P = (int)__builtin_ctzll(tied);
           if (tied & (tied - 1)) {
@@ -353,11 +416,8 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
           const bool upd = !done && lane != P && !bad;
           const double l = upd ? v / d : 0.0;
           S.pl[buf][st][lane] = l;
-          if (lane == 0) {
-            S.pinfo[buf][st] = P | (pp << 8) | ((bad ? 1 : 0) << 16);
-            S.diag[k] = d;
-            S.perm[k] = P;
-          }
+          pinf[st] = P | (pp << 8) | ((bad ? 1 : 0) << 16);
+          dg[st] = d;
           if (bad) break;
           // the rest of the panel (columns k+1 .. of this block)
 #pragma unroll
@@ -369,39 +429,46 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
             R.pos = pp;
           }
         }
+        if (lane == 0) {
+#pragma unroll
+          for (int st = 0; st < 8; ++st) {
+            if (st >= ns) break;
+            S.pinfo[buf][st] = pinf[st];
+            S.diag[k0 + st] = dg[st];
+            S.perm[k0 + st] = pinf[st] & 0xff;
+          }
+        }
       }
     }
     __syncthreads();
-    // replay the panel's steps on this wavefront's other columns and on Y
+    const bool mine = w == owner;
 #pragma unroll
     for (int st = 0; st < 8; ++st) {
       if (st >= ns) break;
-      const int k = k0 + st;
       const int info = __builtin_amdgcn_readfirstlane(S.pinfo[buf][st]);
       if (info >> 16) return false;
-      const int P = info & 0xff, pp = (info >> 8) & 0xff;
-      const bool mine = w == owner;  // the owner's lanes already took this step's bookkeeping
-      // the published multiplier is 0 for the pivot row and the rows pivoted
-      // before, and fma(-0, u, g) is g (up to the sign of a zero g, which no
-      // comparison, pivot or result value sees), so the update needs no select
-      const double l = S.pl[buf][st][lane];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (mine && (j >> 3) == lbo) continue;  // the panel itself
-        R.g[j] = fma(-l, readlane_f64(R.g[j], P), R.g[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) R.y[j] = fma(-l, readlane_f64(R.y[j], P), R.y[j]);
-      if (!mine) {
+      if (!mine) {  // the owner's lanes already took this step's bookkeeping
+        const int P = info & 0xff, pp = (info >> 8) & 0xff;
         if (lane == P) {
-          R.pos = k;
-        } else if (!rdone && R.pos == k) {
+          done = true;
+          R.pos = k0 + st;
+        } else if (!done && R.pos == k0 + st) {
           R.pos = pp;
         }
       }
-      if (lane == P) rdone = true;
     }
-    done = rdone;
+    const bool next_owner = b + 1 < npanels && w == ((b + 1) & 3);
+    if (next_owner) {
+      replay(b, 1, (b + 1) >> 2);
+      owe = b;
+      owe_skip = (b + 1) >> 2;
+    } else {
+      if (owe >= 0) {
+        replay(owe, 0, owe_skip);
+        owe = -1;
+      }
+      replay(b, 0, mine ? lbo : -1);
+    }
   }
   if (live) {
 #pragma unroll
