@@ -310,3 +310,25 @@ def test_tune_cache_round_trip():
     assert torch.equal(g["I"], ref["I"]) and torch.equal(g["J"], ref["J"])
     assert [e["groups"] for e in cur.tune_export()] == [2] * len(t)
     cur.tune_import([])
+
+
+def test_profile_counters_count_the_pass_bytes():
+    """Level 1 times the streaming pass only, level 2 adds the fresh kernel;
+    the algorithmic bytes of one selection are a fixed sum over its launches,
+    and a busy launch is one that moved bytes."""
+    say("case profile counters")
+    A = torch.from_numpy(W.gaussian(1000, 640, 23)).to(DEV)
+    cur.select(A, 16, groups=1)
+    cur.profile_enable(1)
+    cur.select(A, 16, groups=1)
+    p1 = cur.profile_read()
+    cur.profile_enable(2)
+    cur.select(A, 16, groups=1)
+    p2 = cur.profile_read()
+    cur.profile_enable(0)
+    assert p1["launches"] > 0 and 0 < p1["busy"] <= p1["launches"]
+    assert p1["bytes"] > 0 and p1["seconds"] > 0
+    assert p1["fresh_launches"] == 0 and p1["fresh_bytes"] == 0
+    assert p2["bytes"] == p1["bytes"] and p2["launches"] == p1["launches"]
+    assert p2["fresh_launches"] == p2["launches"] and 0 < p2["fresh_busy"] <= p2["fresh_launches"]
+    assert p2["fresh_bytes"] > 0
