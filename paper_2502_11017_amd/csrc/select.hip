@@ -39,20 +39,29 @@ namespace cur {
 constexpr int kTR = 64;
 
 // ---------------------------------------------------------------- a0: input scan
-// max|A| over the matrix and a non-finite flag.  out[0]: max bits (non-negative
-// doubles order like their bit patterns), out[1]: non-finite flag.
+// max|A| and a non-finite flag of every matrix of a call in one launch:
+// grid.y = matrix, workgroups stride over its rows, threads over a row's
+// columns (coalesced, no index division).  out[2 j]: max bits of matrix j
+// (non-negative doubles order like their bit patterns), out[2 j + 1]: its
+// non-finite flag.
+struct ScanItem {
+  const void* A;
+  int64_t m, n, lda;
+};
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_amax(const T* __restrict__ A, int64_t m, int64_t n,
-                                                   int64_t lda, unsigned long long* out) {
+__global__ __launch_bounds__(kThreads) void k_amax(const ScanItem* __restrict__ items, unsigned long long* out) {
+  const ScanItem it = items[blockIdx.y];
+  const T* A = (const T*)it.A;
   double mx = 0.0;
   int bad = 0;
-  const int64_t total = m * n;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx / n, j = idx - i * n;
-    const double v = (double)A[i * lda + j];
-    if (!isfinite(v)) bad = 1;
-    else mx = fmax(mx, fabs(v));
+  for (int64_t i = blockIdx.x; i < it.m; i += gridDim.x) {
+    const T* row = A + i * it.lda;
+    for (int64_t j = threadIdx.x; j < it.n; j += kThreads) {
+      const double v = (double)row[j];
+      if (!isfinite(v)) bad = 1;
+      else mx = fmax(mx, fabs(v));
+    }
   }
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
@@ -71,8 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_amax(const T* __restrict__ A, int6
       mx = fmax(mx, smx[w]);
       bad |= sbad[w];
     }
-    atomicMax(&out[0], (unsigned long long)__double_as_longlong(mx));
-    if (bad) atomicOr(&out[1], 1ull);
+    atomicMax(&out[2 * blockIdx.y], (unsigned long long)__double_as_longlong(mx));
+    if (bad) atomicOr(&out[2 * blockIdx.y + 1], 1ull);
   }
 }
 
@@ -1360,18 +1369,28 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   hipStream_t s = ctx->stream;
   const int nj = (int)jobs.size();
 
-  // ---- a0: scans (one launch per matrix, one synchronization)
+  // ---- a0: scans (one launch for every matrix, one synchronization)
   {
-    cur_status ast = ensure_arena(ctx, 4096 + 16 * (size_t)nj);
+    const size_t items_off = (16 * (size_t)nj + 255) & ~size_t(255);
+    cur_status ast = ensure_arena(ctx, items_off + sizeof(ScanItem) * (size_t)nj);
     if (ast != CUR_OK) return ast;
     unsigned long long* d = (unsigned long long*)ctx->arena;
-    CUR_HIP_CHECK(hipMemsetAsync(d, 0, 16 * (size_t)nj, s));
+    ScanItem* d_items = (ScanItem*)((char*)ctx->arena + items_off);
+    std::vector<ScanItem> hitems(nj);
+    int64_t maxm = 1;
     for (int j = 0; j < nj; ++j) {
-      const TreeJob<T>& jb = jobs[j];
-      const int blocks = (int)std::min<int64_t>(4096, (jb.m * jb.n + kThreads - 1) / kThreads);
-      hipLaunchKernelGGL((k_amax<T>), dim3(std::max(blocks, 1)), dim3(kThreads), 0, s, jb.A, jb.m, jb.n, jb.lda,
-                         d + 2 * j);
+      hitems[j] = {jobs[j].A, jobs[j].m, jobs[j].n, jobs[j].lda};
+      maxm = std::max(maxm, jobs[j].m);
     }
+    CUR_HIP_CHECK(hipMemsetAsync(d, 0, 16 * (size_t)nj, s));
+    CUR_HIP_CHECK(hipMemcpyAsync(d_items, hitems.data(), sizeof(ScanItem) * nj, hipMemcpyHostToDevice, s));
+    // ~16k workgroups in all, at most one per row, at most 4096 per matrix
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(4096, 16384 / nj + 1), maxm));
+    if (nj > 65535) {
+      set_error("too many matrices in one call");
+      return CUR_ERR_ARG;
+    }
+    hipLaunchKernelGGL((k_amax<T>), dim3(gx, nj), dim3(kThreads), 0, s, d_items, d);
     std::vector<unsigned long long> hv(2 * (size_t)nj);
     CUR_HIP_CHECK(hipMemcpyAsync(hv.data(), d, 16 * (size_t)nj, hipMemcpyDeviceToHost, s));
     CUR_HIP_CHECK(hipStreamSynchronize(s));
