@@ -810,3 +810,106 @@ int oracle_cur_residual(const double* A, int64_t m, int64_t n, int64_t lda, int 
   if (fro_rel) *fro_rel = (asq > 0.0) ? sqrt(esq) / sqrt(asq) : 0.0;
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Norm-greedy selection (Alg. 2 with Alg. 3)                                */
+/* ------------------------------------------------------------------------ */
+/*
+ * Alg. 3 on one axis: r times, the candidate vector (column, or row) of
+ * largest Euclidean norm is chosen (strict '>' in ascending index order, so
+ * the first maximum wins) and projected out of every vector:
+ *     v <- v - ((s . v) / (s . s)) s
+ * (the division by the squared norm of s, the reading that makes this the
+ * orthogonal projection; the listing's "maxNorm" is ambiguous).  Norms are
+ * compared squared (same order), a chosen vector is no candidate again (its
+ * projection is zero in exact arithmetic), and the selection stops early,
+ * rank-short, once the largest remaining squared norm is at most
+ * (max(m,n) 2^-52)^2 times the largest initial one.  The block partition of
+ * Alg. 3 only distributes the argmax and the update; it does not change the
+ * result, so the oracle works on the whole matrix.
+ *
+ * Every sum over a vector (dot products, squared norms) is taken in one fixed
+ * order: 64 partial sums, partial l accumulating the elements i = l, l + 64,
+ * ... in ascending order with fma, then combined pairwise by a xor butterfly
+ * (distances 32, 16, 8, 4, 2, 1).  The update of an element is one fma with
+ * the coefficient c = (s . v) / (s . s).
+ */
+static double lane_sum_dot(const double* a, const double* b, int64_t len) {
+  double p[64], q[64];
+  for (int l = 0; l < 64; ++l) p[l] = 0.0;
+  for (int64_t i = 0; i < len; ++i) p[i & 63] = fma(a[i], b[i], p[i & 63]);
+  for (int d = 32; d >= 1; d >>= 1) {
+    for (int l = 0; l < 64; ++l) q[l] = p[l] + p[l ^ d];
+    for (int l = 0; l < 64; ++l) p[l] = q[l];
+  }
+  return p[0];
+}
+
+/* Vectors W[v * len + i] (cnt of them, contiguous); order[t] receives the
+ * chosen vector of step t.  Returns the number chosen (<= r). */
+static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* order) {
+  double* nrm = (double*)malloc(sizeof(double) * (size_t)cnt);
+  char* sel = (char*)calloc((size_t)cnt, 1);
+  double nmax0 = 0.0;
+  for (int64_t v = 0; v < cnt; ++v) {
+    nrm[v] = lane_sum_dot(W + v * len, W + v * len, len);
+    if (nrm[v] > nmax0) nmax0 = nrm[v];
+  }
+  const double eps = (double)(len > cnt ? len : cnt) * ldexp(1.0, -52);
+  const double theta = eps * eps * nmax0;
+  int t = 0;
+  for (; t < r; ++t) {
+    int64_t j = -1;
+    double best = -1.0;
+    for (int64_t v = 0; v < cnt; ++v)
+      if (!sel[v] && nrm[v] > best) {
+        best = nrm[v];
+        j = v;
+      }
+    if (j < 0 || !(best > theta)) break;
+    sel[j] = 1;
+    order[t] = j;
+    const double* s = W + j * len;
+    const double ss = nrm[j];
+    for (int64_t v = 0; v < cnt; ++v) {
+      if (sel[v]) continue;
+      double* w = W + v * len;
+      const double c = lane_sum_dot(s, w, len) / ss;
+      for (int64_t i = 0; i < len; ++i) w[i] = fma(-c, s[i], w[i]);
+      nrm[v] = lane_sum_dot(w, w, len);
+    }
+  }
+  free(nrm);
+  free(sel);
+  return t;
+}
+
+/*
+ * Alg. 2 by Alg. 3: rows I and columns J chosen independently by the
+ * norm-greedy rule.  A is m x n row-major (lda).  order_I / order_J (r each)
+ * receive the choice order, I and J the same indices ascending; entries past
+ * the rank reached are -1.  Returns ORC_OK, or ORC_ERR_RANK when either axis
+ * stops short (*rank_rows / *rank_cols say where).
+ */
+int oracle_greedy_select(const double* A, int64_t m, int64_t n, int64_t lda, int r, int64_t* order_I,
+                         int64_t* order_J, int64_t* I, int64_t* J, int* rank_rows, int* rank_cols) {
+  if (!A || m < 1 || n < 1 || lda < n || r < 1 || r > m || r > n) return ORC_ERR_ARG;
+  double* W = (double*)malloc(sizeof(double) * (size_t)(m * n));
+  if (!W) return ORC_ERR_NOMEM;
+  for (int64_t i = 0; i < r; ++i) order_I[i] = order_J[i] = I[i] = J[i] = -1;
+  /* rows: vector i = A(i, :) */
+  for (int64_t i = 0; i < m; ++i) memcpy(W + i * n, A + i * lda, sizeof(double) * (size_t)n);
+  const int qr = greedy_axis(W, n, m, r, order_I);
+  /* columns: vector j = A(:, j) */
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < n; ++j) W[j * m + i] = A[i * lda + j];
+  const int qc = greedy_axis(W, m, n, r, order_J);
+  free(W);
+  for (int t = 0; t < qr; ++t) I[t] = order_I[t];
+  for (int t = 0; t < qc; ++t) J[t] = order_J[t];
+  sort_i64(I, qr);
+  sort_i64(J, qc);
+  *rank_rows = qr;
+  *rank_cols = qc;
+  return (qr < r || qc < r) ? ORC_ERR_RANK : ORC_OK;
+}

@@ -76,6 +76,8 @@ def lib():
         L.oracle_cur_assemble.restype = i32
         L.oracle_cur_residual.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P]
         L.oracle_cur_residual.restype = i32
+        L.oracle_greedy_select.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P, P]
+        L.oracle_greedy_select.restype = i32
         _lib = L
     return _lib
 
@@ -249,3 +251,22 @@ def select_raw(A, r, w=0, tau=0.0, max_swaps=0):
     rc = lib().oracle_cur_select(_p(A), m, n, n, r, int(w), float(tau), int(max_swaps), _p(I), _p(J),
                                  ctypes.byref(info), None, None, None, None)
     return rc, info, I, J
+
+
+def greedy(A, r):
+    """Norm-greedy selection of rows and columns (Alg. 2 with Alg. 3), see
+    oracle_greedy_select: choice orders, ascending I and J, status, ranks."""
+    A = _f64(A)
+    m, n = A.shape
+    oI = np.full(r, -1, np.int64)
+    oJ = np.full(r, -1, np.int64)
+    I = np.full(r, -1, np.int64)
+    J = np.full(r, -1, np.int64)
+    qr = ctypes.c_int(0)
+    qc = ctypes.c_int(0)
+    st = lib().oracle_greedy_select(_p(A), m, n, n, r, _p(oI), _p(oJ), _p(I), _p(J), ctypes.byref(qr),
+                                    ctypes.byref(qc))
+    if st == ERR_ARG:
+        raise ValueError("oracle_greedy_select: invalid argument")
+    return {"order_I": oI, "order_J": oJ, "I": I, "J": J, "status": st, "rank_rows": qr.value,
+            "rank_cols": qc.value}
