@@ -87,6 +87,12 @@ typedef struct {
   const void* mlp;     /* reserved (must be NULL when propose == 0)                              */
   uint64_t seed;       /* reserved                                                               */
   cur_trace* trace;    /* host pointer or NULL: per-node tree records                            */
+  int32_t method;      /* 0: maximal-volume tree (Alg. 1 leaves, swap loops, binary merge);
+                          1: norm-greedy rows and columns (Alg. 2 with Alg. 3): r times the
+                          row (column) of largest norm, projected out of all rows (columns);
+                          col_block, tau, max_swaps, groups and trace do not apply, info->logvol
+                          is NaN, and cur_select_batched rejects it                              */
+  int32_t reserved1;
 } cur_opts;
 
 typedef struct {

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libcur.so")
 
 OK, WARN_NOCONV = 0, 1
 ERR_ARG, ERR_RANK, ERR_NONFINITE, ERR_DEVICE, ERR_NOMEM, ERR_INTERNAL = -1, -2, -3, -4, -5, -6
+METHOD_MAXVOL, METHOD_GREEDY = 0, 1
 F64, F32 = 0, 1
 PREC_NATIVE, PREC_BF16X3, PREC_FP8 = 0, 1, 2
 TRACE_FIELDS = ("level", "index", "q", "short", "promoted", "nocap", "swaps", "phases",
@@ -49,7 +50,7 @@ class Opts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("max_swaps", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("propose", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("seed", ctypes.c_uint64),
-                ("trace", ctypes.POINTER(Trace))]
+                ("trace", ctypes.POINTER(Trace)), ("method", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -170,10 +171,11 @@ def _matrix(A):
     return A.shape[0], A.shape[1], A.stride(0)
 
 
-def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None, groups=0) -> Opts:
+def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None, groups=0, method=0) -> Opts:
     o = Opts()
     lib().cur_opts_init(ctypes.byref(o))
     o.groups = int(groups)
+    o.method = int(method)
     o.col_block = int(col_block)
     o.tau = float(tau)
     o.max_swaps = int(max_swaps)
@@ -194,7 +196,7 @@ def tree_size(n: int, w: int) -> int:
 
 
 def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, trace: bool = False,
-           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0):
+           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0, method: int = METHOD_MAXVOL):
     """Select r rows I and r columns J of the device matrix A (cur_select)."""
     torch = _torch()
     m, n, lda = _matrix(A)
@@ -213,7 +215,7 @@ def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, 
                 "I": np.zeros((N, r), dtype=np.int64), "J": np.zeros((N, r), dtype=np.int64)}
         tr = Trace(N, 0, host["meta"].ctypes.data, host["vol_m"].ctypes.data,
                    host["I"].ctypes.data, host["J"].ctypes.data)
-    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups)
+    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups, method=method)
     rc = lib().cur_select(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
                           ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                           ctypes.byref(info))

@@ -84,6 +84,8 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.prec < CUR_PREC_NATIVE || o.prec > CUR_PREC_FP8) return arg_error("prec out of range");
   if (o.propose != 0) return arg_error("propose must be 0 in this build");
   if (o.groups < 0 || o.groups > 3) return arg_error("groups must be 0 (autotuned) or 1..3");
+  if (o.method != 0 && o.method != 1) return arg_error("method must be 0 (maximal volume) or 1 (norm-greedy)");
+  if (o.method == 1 && o.trace) return arg_error("trace is not available for the norm-greedy method");
   if (o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
   if (o.trace) {
     int64_t b = n / o.col_block;
@@ -207,6 +209,7 @@ cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, in
   if (!ctx) return arg_error("ctx is NULL");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
+  if (o.method == 1) return greedy_dispatch(ctx, dtype, A, m, n, lda, r, I, J, info);
   return select_dispatch(ctx, dtype, A, m, n, lda, r, o, I, J, info);
 }
 
@@ -299,6 +302,8 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
   if (count < 0) return arg_error("count must be >= 0");
   if (count > 0 && !items) return arg_error("items is NULL");
   if (opts && opts->trace) return arg_error("opts->trace must be NULL for batched selection");
+  if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->method != 0)
+    return arg_error("batched selection supports the maximal-volume method only");
   for (int32_t i = 0; i < count; ++i) {
     const cur_item& it = items[i];
     cur_status st = check_matrix((cur_dtype)it.dtype, it.A, it.m, it.n, it.lda, it.r);

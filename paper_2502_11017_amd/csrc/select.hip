@@ -1134,7 +1134,7 @@ static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, 
 
 // Streams and events of the node groups, created once per context.
 constexpr int kMaxGroups = 4;
-static cur_status ensure_groups(cur_ctx ctx) {
+cur_status ensure_groups(cur_ctx ctx) {
   if (ctx->groups_ready) return CUR_OK;
   for (int g = 0; g < kMaxGroups; ++g) {
     CUR_HIP_CHECK(hipStreamCreateWithFlags(&ctx->gstream[g], hipStreamNonBlocking));

@@ -69,7 +69,7 @@ def test_select_argument_errors_on_host(kw, msg):
     ("col_block", 2, "col_block must be >= r"), ("col_block", -1, "col_block"),
     ("tau", -1.0, "tau"), ("max_swaps", -3, "max_swaps"), ("prec", 9, "prec"),
     ("propose", 1, "propose"), ("struct_size", 8, "struct_size"),
-    ("groups", 4, "groups"), ("groups", -1, "groups"),
+    ("groups", 4, "groups"), ("groups", -1, "groups"), ("method", 2, "method"),
 ])
 def test_select_option_errors_on_host(field, value, msg):
     o = cur.make_opts()
@@ -123,3 +123,15 @@ def test_tune_cache_argument_errors():
     assert L.cur_tune_export(None, None, 0, ctypes.byref(n)) == cur.ERR_ARG
     assert L.cur_tune_import(None, None, 0) == cur.ERR_ARG
     assert L.cur_profile_enable(None, 1) == cur.ERR_ARG
+
+
+def test_greedy_method_rejects_trace_and_batching():
+    o = cur.make_opts(method=1)
+    tr = cur.Trace(1, 0, None, None, None, None)
+    o.trace = ctypes.pointer(tr)
+    assert _sel(opts=o) == cur.ERR_ARG and "trace" in cur.last_error()
+    o = cur.make_opts(method=1)
+    L = cur.lib()
+    items = (cur.Item * 1)(cur.Item(cur.F64, 3, 1, 10, 12, 12, 1, 1))
+    assert L.cur_select_batched(None, 1, items, ctypes.byref(o), None) == cur.ERR_ARG
+    assert "maximal-volume" in cur.last_error()

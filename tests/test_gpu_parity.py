@@ -332,3 +332,50 @@ def test_profile_counters_count_the_pass_bytes():
     assert p2["bytes"] == p1["bytes"] and p2["launches"] == p1["launches"]
     assert p2["fresh_launches"] == p2["launches"] and 0 < p2["fresh_busy"] <= p2["fresh_launches"]
     assert p2["fresh_bytes"] > 0
+
+
+GREEDY_CASES = [
+    # (m, n, r, seed, dtype)
+    (200, 300, 8, 31, torch.float64),
+    (513, 700, 16, 32, torch.float64),   # m not a multiple of 64
+    (64, 64, 64, 33, torch.float64),     # r = min(m, n)
+    (777, 129, 1, 34, torch.float64),    # r = 1
+    (600, 900, 24, 35, torch.float32),   # FP32 input, exact upcast for the oracle
+]
+
+
+@pytest.mark.parametrize("m,n,r,seed,dt", GREEDY_CASES)
+def test_greedy_matches_oracle(orc, m, n, r, seed, dt):
+    """Norm-greedy rows and columns (Alg. 2 with Alg. 3): same index sets and
+    status as the oracle, bit for bit (same sums in the same order)."""
+    A = torch.from_numpy(W.gaussian(m, n, seed)).to(dt).to(DEV)
+    say(f"case greedy m={m} n={n} r={r} seed={seed} {dt}")
+    g = cur.select(A, r, method=cur.METHOD_GREEDY)
+    o = orc.greedy(A.cpu().numpy(), r)
+    assert g["status"] == o["status"]
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    assert np.isnan(g["logvol"])
+
+
+def test_greedy_rank_short_and_c2_recipe(orc):
+    rng = np.random.default_rng(36)
+    A = torch.from_numpy(rng.standard_normal((400, 6)) @ rng.standard_normal((6, 500))).to(DEV)
+    say("case greedy rank-short")
+    g = cur.select(A, 10, method=cur.METHOD_GREEDY)
+    o = orc.greedy(A.cpu().numpy(), 10)
+    assert g["status"] == o["status"] == cur.ERR_RANK and g["rank"] == 6
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    A = W.c2(37, device=DEV, n=1024)
+    say("case greedy c2-recipe n=1024 r=64")
+    g = cur.select(A, 64, method=cur.METHOD_GREEDY)
+    o = orc.greedy(A.cpu().numpy(), 64)
+    assert g["status"] == o["status"]
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    B = A.clone()
+    B[5, 9] = float("nan")
+    with pytest.raises(cur.CurError) as ei:
+        cur.select(B, 8, method=cur.METHOD_GREEDY)
+    assert ei.value.status == cur.ERR_NONFINITE
