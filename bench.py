@@ -138,6 +138,32 @@ def bench_e2(cur, W, torch, dev, reps=2):
     return out
 
 
+def bench_f1(cur, torch, A, r, res_maxvol, reps=3):
+    """The paper's literal norm-greedy selection (Alg. 2 with Alg. 3, rows and
+    columns independently) on the same C2 matrix; its cross volume against
+    the maximal-volume selection's (log|det| of the r x r crosses, host LU)."""
+    import numpy as np
+
+    cur.select(A, r, method=cur.METHOD_GREEDY)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        g = cur.select(A, r, method=cur.METHOD_GREEDY)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+
+    def logvol(I, J):
+        G = A[I][:, J].double().cpu().numpy()
+        return float(np.linalg.slogdet(G)[1])
+
+    lg, lm = logvol(g["I"], g["J"]), logvol(res_maxvol["I"], res_maxvol["J"])
+    out = {"workload": "C2 (same matrix), rows and columns by the norm-greedy rule, FP64",
+           "select_ms": 1e3 * dt, "selections_per_s": 1.0 / dt, "status": g["status"],
+           "logvol_greedy": lg, "logvol_maxvol": lm, "volume_ratio_greedy_over_maxvol": float(np.exp(lg - lm))}
+    log(f"f1: norm-greedy {1e3 * dt:.1f} ms, volume ratio to the maximal-volume cross {out['volume_ratio_greedy_over_maxvol']:.3e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +179,7 @@ def main():
     ap.add_argument("--no-e1", action="store_true",
                     help="skip the reduced-precision residual figures on the tall FP32 workload")
     ap.add_argument("--no-e2", action="store_true", help="skip the batched uneven-workload figures")
+    ap.add_argument("--no-f1", action="store_true", help="skip the norm-greedy (paper-literal) selection figures")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of the launch autotuner cache: loaded before the run when it exists, "
                          "written at the end (profiling runs reuse the tuned launch shapes)")
@@ -281,6 +308,9 @@ def main():
                 - orc.logvol(A32h, I, J)))
         del A32
 
+    f1 = None
+    if not args.no_f1:
+        f1 = bench_f1(cur, torch, A, r, res)
     e1 = None
     if not args.no_e1:
         e1 = bench_e1(cur, W, torch, dev)
@@ -324,6 +354,7 @@ def main():
         "f32": f32,
         "e1_reduced_precision_residual": e1,
         "e2_batched_uneven": e2,
+        "f1_paper_greedy": f1,
         "cpu_baseline": cpu,
     }
     if args.tune_cache:
