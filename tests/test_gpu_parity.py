@@ -379,3 +379,15 @@ def test_greedy_rank_short_and_c2_recipe(orc):
     with pytest.raises(cur.CurError) as ei:
         cur.select(B, 8, method=cur.METHOD_GREEDY)
     assert ei.value.status == cur.ERR_NONFINITE
+
+
+def test_error_curve_points_decrease():
+    """The paper's Hilbert workload: the Frobenius error of both methods falls
+    as r grows (and stays below 1)."""
+    from paper_2502_11017_amd import curves
+
+    A = torch.from_numpy(W.hilbert(256)).to(DEV)
+    say("case error curve hilbert 256")
+    for method in (cur.METHOD_MAXVOL, cur.METHOD_GREEDY):
+        fros = [curves.point(A, r, method)[1] for r in (2, 4, 8)]
+        assert fros[0] < 1.0 and fros[0] > fros[1] > fros[2], (method, fros)
