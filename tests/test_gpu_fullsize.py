@@ -109,3 +109,75 @@ def test_fullsize_f32_volume_ratio(orc, c2_pair):
     ratio = np.exp(orc.logvol(Ah32, gI, gJ) - orc.logvol(Ah32, o32["I"], o32["J"]))
     say(f"  volume ratio {ratio:.6f}")
     assert ratio >= 0.99
+
+
+def test_fullsize_batched_uneven_sampled_items(orc):
+    # the 256-matrix uneven FP32 batch in one batched call; 8 seeded items
+    # against the oracle's FP64 selection of the upcast matrix
+    specs = W.c3_specs()
+    say(f"case batched uneven: {len(specs)} FP32 matrices, one batched call")
+    As = [W.c3_matrix(sp, device=DEV, dtype=torch.float32) for sp in specs]
+    rs = [sp[2] for sp in specs]
+    outs, _ = cur.select_batched(As, rs)
+    ok = [k for k, (_, _, st) in enumerate(outs) if st in (cur.OK, cur.WARN_NOCONV)]
+    assert len(ok) >= 240
+    rng = np.random.default_rng(17)
+    for k in sorted(rng.choice(ok, 8, replace=False)):
+        I, J, st = outs[k]
+        Ah = As[k].cpu().numpy().astype(np.float64)
+        r = rs[k]
+        gI, gJ = I.cpu().numpy(), J.cpu().numpy()
+        assert len(set(gI)) == r and len(set(gJ)) == r
+        o = orc.select(Ah, r)
+        ratio = np.exp(orc.logvol(Ah, gI, gJ) - orc.logvol(Ah, o["I"], o["J"]))
+        say(f"  item {k}: {Ah.shape[0]} x {Ah.shape[1]} r={r} status {st} volume ratio {ratio:.6f}")
+        assert ratio >= 0.99
+
+
+def test_fullsize_tall_residual_forms(orc):
+    # the tall 2^20 x 1024 FP32 low-rank-128 workload, r = 128: the native
+    # residual and the BF16x3 / FP8 forms against the FP64 definition over all
+    # entries and the oracle on sampled rows (with the row of the largest
+    # error); bounds as in the reduced-height tests
+    m, n, r = 1 << 20, 1024, 128
+    say(f"case tall residual m={m} n={n} r={r} FP32")
+    A = W.c4(seed=4, device=DEV, m=m, n=n, k=128)
+    res = cur.select(A, r)
+    assert res["status"] in (cur.OK, cur.WARN_NOCONV)
+    C, U, Rm = cur.assemble(A, res["I"], res["J"])
+    Ch = C.cpu().numpy().astype(np.float64)
+    Uh = U.cpu().numpy()
+    Rh = Rm.cpu().numpy().astype(np.float64)
+    Af = A.cpu().numpy()
+    emax, erow, esq, asq, amax, S = 0.0, 0, 0.0, 0.0, 0.0, 0.0
+    for i0 in range(0, m, 1 << 16):
+        Ai = Af[i0:i0 + (1 << 16)].astype(np.float64)
+        Bm = Ch[i0:i0 + (1 << 16)] @ Uh
+        E = Ai - Bm @ Rh
+        ae = np.abs(E).max(axis=1)
+        if ae.max() > emax:
+            emax, erow = float(ae.max()), i0 + int(ae.argmax())
+        esq += float((E * E).sum())
+        asq += float((Ai * Ai).sum())
+        amax = max(amax, float(np.abs(Ai).max()))
+        S = max(S, float(np.abs(Bm).sum(axis=1).max()))
+    S *= amax
+    fro_def = np.sqrt(esq) / np.sqrt(asq)
+    rows = np.union1d(np.random.default_rng(6).choice(m, 255, replace=False), [erow])
+    ocheb, _ = orc.residual(Af[rows].astype(np.float64), np.ascontiguousarray(Ch[rows]), Uh, Rh)
+    rms_a = np.sqrt(asq / (m * n))
+    say(f"  definition cheb {emax:.6e} fro {fro_def:.6e}; oracle on sampled rows {ocheb:.6e}")
+    assert abs(ocheb - emax) <= 1e-10 * amax
+    for prec, name in ((cur.PREC_NATIVE, "native"), (cur.PREC_BF16X3, "bf16x3"), (cur.PREC_FP8, "fp8")):
+        cheb, fro = cur.residual(A, C, U, Rm, prec)
+        if prec == cur.PREC_NATIVE:
+            cb, fb = 1e-10 * amax, 1e-10 * max(1.0, fro_def)
+        elif prec == cur.PREC_BF16X3:
+            cb = (3 * 2.0**-17 + 3 * r * 2.0**-24) * S
+            fb = cb / rms_a
+        else:
+            cb = 2.0**-6 * S
+            fb = cb / rms_a
+        say(f"  {name}: cheb {cheb:.6e} |d| {abs(cheb - emax):.3e} (bound {cb:.3e}); fro {fro:.6e}")
+        assert abs(cheb - emax) <= cb
+        assert abs(fro - fro_def) <= fb
