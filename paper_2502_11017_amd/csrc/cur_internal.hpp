@@ -15,6 +15,10 @@ constexpr int kThreads = 256;      // threads per workgroup of every kernel here
 constexpr int kTileRows = 256;     // rows of a row-pass tile (one row per thread)
 constexpr int kMetaFields = 10;    // fields of a cur_trace meta record
 constexpr int kDbgRing = 64;       // swap decisions remembered per node
+// Row swaps whose Sherman-Morrison updates a pass applies on the fly instead
+// of holding them in the working matrix (the pass after the last of them
+// writes the matrix out again).
+constexpr int kLz = 4;
 
 // Per-node state machine.  A node is a leaf (one column block), a merge of two
 // children, or a promoted copy of an odd last child.
@@ -63,6 +67,9 @@ struct Node {
   int64_t* I;        // r: selected rows (current order)
   int32_t* Jp;       // r: selected candidate positions (current order)
   double* dbg;       // 4 x kDbgRing swap log (kind, index, slot, pivot) for diagnostics
+  void* lzg;         // kLz x m, column s (ld m), element T: the column g_s = B(:, k_s)
+                     // before row swap s of the pending history
+  double* lzv;       // kLz x r row-major: the factors v_s of those swaps
   const void* src;   // leaves: the matrix A this tree selects from (element T)
   int64_t lda;       // leaves: its leading dimension
   int64_t col0;      // leaves: first column of the block
@@ -82,7 +89,9 @@ struct Node {
   double pend_p;     // pending pivot value
   double vol_m;      // volume mantissa (finished nodes)
   int32_t vol_e;     // volume exponent
-  int32_t pad1;
+  int32_t lz;        // row swaps pending in the history (their updates are not in `work`)
+  int64_t lzi[kLz];  // row swapped in by each pending swap
+  int32_t lzk[kLz];  // its slot k
 };
 
 // Host-side error reporting (thread-local last error).

@@ -294,23 +294,45 @@ void k_pass(Node* nodes, unsigned long long* prof) {
     }
     ab.to_cand(best, row, nc);
   } else {
-    // B <- B - B(:, ks) v^T, row is set to e_ks^T.  No mask of the selected
-    // rows here: a selected row is exactly e_k, the update keeps it so (its
-    // entry in column ks is 0, and fma(-0, v, x) = x), and |e_k| <= 1 < 1 + tau,
-    // so such a row can win a tile only when no row swap is due, where the
+    // B <- B - B(:, ks) v^T, row is set to e_ks^T.  The working matrix holds
+    // B before the S = nd.lz pending swaps of the history; every element is
+    // rebuilt by replaying them (g_q = the row's entry of B(:, k_q) before
+    // swap q, kept per swap) and then this swap, each step the in-place
+    // update's own operation, so the values equal those of updating B in
+    // place.  This swap's g goes to the history; the pass that fills the
+    // last slot writes B out instead.  No mask of the selected rows here: a
+    // selected row is exactly e_k, the update keeps it so (its entry in
+    // column ks is 0, and fma(-0, v, x) = x), and |e_k| <= 1 < 1 + tau, so
+    // such a row can win a tile only when no row swap is due, where the
     // winner's identity is not used.
     const int ks = nd.pend_k;
     const int64_t is = nd.pend_i;
-    T vr[4];
-    {
-      double vd[4];
-      lane_load(vd, nd.vec, r);  // r <= 128 < kLaneCols
+    const int S = nd.lz;
+    const bool wout = S == kLz - 1;
+    __shared__ double sv[kLz * RMAX];  // v_q(c) at q * r + c, q <= S
+    for (int idx = tid; idx < (S + 1) * r; idx += kThreads) sv[idx] = nd.lzv[idx];
+    const GPtr<T> G = (GPtr<T>)nd.lzg;
+    T gq[kLz - 1];
+    int64_t iq[kLz - 1];
+    int kq[kLz - 1];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) vr[q] = (T)vd[q];
+    for (int q = 0; q < kLz - 1; ++q) {
+      gq[q] = (q < S) ? col_ld<T>(G + (int64_t)q * m, ro) : (T)0;
+      iq[q] = nd.lzi[q];
+      kq[q] = nd.lzk[q];
     }
+    __syncthreads();
+    // the pending swaps applied to one element (row, c) of the working matrix
+    auto replay = [&](T x, int c) {
+#pragma unroll
+      for (int q = 0; q < kLz - 1; ++q)
+        if (q < S) x = (row == iq[q]) ? ((c == kq[q]) ? (T)1 : (T)0) : fma_t<T>(-gq[q], (T)sv[q * r + c], x);
+      return x;
+    };
+    const T g = replay(col_ld<T>(W + (int64_t)ks * m, ro), ks);
+    if (!wout && valid) col_st<T>(G + (int64_t)S * m, ro, g);
     RowBest<T> rb;
     {
-      const T g = col_ld<T>(W + (int64_t)ks * m, ro);
       // all rounds unrolled (r <= RMAX): no loop header at which the compiler
       // would wait for every outstanding load
 #pragma unroll
@@ -323,15 +345,14 @@ void k_pass(Node* nodes, unsigned long long* prof) {
           const int cc = min(c0 + u, r - 1);  // in range; extra lanes of the round are ignored
           bs[u] = col_ld<T>(W + (int64_t)cc * m, ro);
         }
-        const T vq = lane_reg(vr, c0 >> 6);
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
           const int c = c0 + u;
           if (c < r) {
-            T b = fma_t<T>(-g, lane_read(vq, c & 63), bs[u]);
+            T b = fma_t<T>(-g, (T)sv[S * r + c], replay(bs[u], c));
             if (row == is) b = (c == ks) ? (T)1 : (T)0;
             if (valid) {
-              col_st<T>(W + (int64_t)c * m, ro, b);
+              if (wout) col_st<T>(W + (int64_t)c * m, ro, b);
               rb.take(b, c);
             }
           }
@@ -341,9 +362,9 @@ void k_pass(Node* nodes, unsigned long long* prof) {
     rb.to_cand(best, row, r);
   }
 
-  int64_t cols;  // algorithmic columns: working columns read + columns written
+  int64_t cols;  // algorithmic columns: working and history columns read + columns written
   if (st == ST_ACA) cols = (nd.t == 0) ? nd.na : 2 * nd.na - 1;
-  else cols = 2 * (int64_t)r;
+  else cols = (int64_t)r + nd.lz + ((nd.lz == kLz - 1) ? r : 1);
   pass_finish(nd, tile, best, sc, prof, m * cols * (int64_t)sizeof(T));
 }
 

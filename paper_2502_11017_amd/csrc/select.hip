@@ -259,6 +259,7 @@ struct CtlShared {
   double pend_p;
   double vol_m;
   int vol_e;
+  int lz;
   int spiv;
   int wtile;
   Cand win;
@@ -821,6 +822,13 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     s.phase_swaps = nd.phase_swaps; s.since = nd.since; s.swaps = nd.swaps; s.phases = nd.phases;
     s.refreshes = nd.refreshes; s.pend_k = nd.pend_k; s.pend_i = nd.pend_i; s.pend_p = nd.pend_p;
     s.vol_m = nd.vol_m; s.vol_e = nd.vol_e;
+    // the pass that just ran: a fresh B empties the swap history; a swap pass
+    // added one swap to it, or wrote B out with all of them (the last slot)
+    s.lz = nd.lz;
+    if (!startup) {
+      if (s.st == ST_ROW_FRESH) s.lz = 0;
+      else if (s.st == ST_ROW_SWAP) s.lz = (s.lz + 1 == kLz) ? 0 : s.lz + 1;
+    }
     s.mode = M_EXIT;
     s.stale = 0;
   }
@@ -905,12 +913,25 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     }
     __syncthreads();
     if (L.s.mode == M_SWAPVEC) {
+      // v_c = B(i*, c) / p with row i* of the current B: the working matrix
+      // plus the pending swaps, replayed in the pass's own operation order
       const T* B = (const T*)nd.work;
+      const T* G = (const T*)nd.lzg;
       const int64_t wr = L.s.pend_i;
       const T p = (T)L.s.pend_p;
       const int ks = L.s.pend_k;
-      for (int c = tid; c < r; c += kThreads)
-        nd.vec[c] = (c == ks) ? (double)((p - (T)1) / p) : (double)(B[(int64_t)c * m + wr] / p);
+      const int S = L.s.lz;
+      for (int c = tid; c < r; c += kThreads) {
+        T x = B[(int64_t)c * m + wr];
+        for (int q = 0; q < S; ++q)
+          x = (wr == nd.lzi[q]) ? ((c == nd.lzk[q]) ? (T)1 : (T)0)
+                                : fma_t<T>(-G[(int64_t)q * m + wr], (T)nd.lzv[q * r + c], x);
+        nd.lzv[S * r + c] = (c == ks) ? (double)((p - (T)1) / p) : (double)(x / p);
+      }
+      if (tid == 0) {
+        nd.lzi[S] = wr;
+        nd.lzk[S] = ks;
+      }
       __syncthreads();
       if (tid == 0) L.s.mode = M_EXIT;
       __syncthreads();
@@ -1031,6 +1052,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     nd.phase_swaps = s.phase_swaps; nd.since = s.since; nd.swaps = s.swaps; nd.phases = s.phases;
     nd.refreshes = s.refreshes; nd.pend_k = s.pend_k; nd.pend_i = s.pend_i; nd.pend_p = s.pend_p;
     nd.vol_m = s.vol_m; nd.vol_e = s.vol_e;
+    nd.lz = s.lz;
   }
 }
 
@@ -1480,6 +1502,8 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     per += al(nc);                                // insel
     per += al(sizeof(int64_t) * r) + al(sizeof(int32_t) * r);
     per += al(sizeof(double) * 4 * kDbgRing);
+    per += al(sizeof(T) * m * kLz);               // swap history: columns g_s
+    per += al(sizeof(double) * kLz * r);          // swap history: factors v_s
     return per;
   };
   size_t bytes = 4096;  // done counters (16 per level)
@@ -1538,7 +1562,9 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
         nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
         nd.dbg = (double*)ar.take(sizeof(double) * 4 * kDbgRing);
-        if (!nd.panel || !nd.work || !nd.insel || !nd.Jp || !nd.dbg) {
+        nd.lzg = ar.take(sizeof(T) * jb.m * kLz);
+        nd.lzv = (double*)ar.take(sizeof(double) * kLz * r);
+        if (!nd.panel || !nd.work || !nd.insel || !nd.Jp || !nd.dbg || !nd.lzv) {
           set_error("workspace layout overflow");
           return CUR_ERR_INTERNAL;
         }
