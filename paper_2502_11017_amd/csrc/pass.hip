@@ -372,8 +372,10 @@ void k_pass(Node* nodes, unsigned long long* prof) {
 // row-major), rows I set to unit rows, fused with the tile's argmax over the
 // other rows.  Every output is the FP64 sum over k ascending of
 // A(row, Jp_k) X(k, c).  X is staged in LDS CB columns at a time (broadcast
-// reads); A(row, Jp_k) is read 8 columns at a time per chunk, from L2 after
-// the first chunk.  Its own kernel: the product wants registers that would
+// reads): for r <= 64 all of it, so each A(row, Jp_k) is loaded once, U of
+// them in flight, and each thread accumulates its whole row of B in
+// registers; for larger r 16 columns at a time, A(row, Jp_k) re-read per
+// chunk from L2.  Its own kernel: the product wants registers that would
 // cost the streaming pass its residency.
 template <typename T, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long long* prof) {
@@ -390,7 +392,8 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   T* W = (T*)nd.work;
   const T* P = (const T*)nd.panel;
 
-  constexpr int CB = 16;  // columns of X staged per chunk
+  constexpr int CB = RMAX <= 64 ? RMAX : 16;  // columns of X staged per chunk
+  constexpr int U = RMAX <= 64 ? 16 : 8;      // loads of A(row, Jp_k) in flight
   __shared__ double sX[RMAX * CB];
   __shared__ int sJp[RMAX];
   __shared__ int sslot[kTileRows];
@@ -417,7 +420,6 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
       double acc[CB];
 #pragma unroll
       for (int j = 0; j < CB; ++j) acc[j] = 0.0;
-      constexpr int U = 8;
       for (int k0 = 0; k0 < r; k0 += U) {
         double pk[U];
 #pragma unroll
