@@ -78,6 +78,7 @@ def _spawn(args, env=None, timeout=600) -> str:
 
 def sweep(n=16384, r=64, cus=(32, 64, 128, 256), steps=3, warmup=3, seed=2, workdir=None):
     """Rows {cus, ms, status, swaps, digest} of one selection per CU count."""
+    own = workdir is None
     workdir = workdir or tempfile.mkdtemp(prefix="cusweep_")
     path = os.path.join(workdir, f"c2_{n}.npy")
     if not os.path.exists(path):
@@ -94,6 +95,8 @@ def sweep(n=16384, r=64, cus=(32, 64, 128, 256), steps=3, warmup=3, seed=2, work
         print(f"cus {k:>4}  {d['ms']:9.2f} ms  status {d['status']}  swaps {d['swaps']}  I,J {d['digest']}",
               flush=True)
     os.remove(path)
+    if own:
+        os.rmdir(workdir)
     return rows
 
 
