@@ -309,8 +309,22 @@ void k_pass(Node* nodes, unsigned long long* prof) {
     const int64_t is = nd.pend_i;
     const int S = nd.lz;
     const bool wout = S == kLz - 1;
-    __shared__ double sv[kLz * RMAX];  // v_q(c) at q * r + c, q <= S
-    for (int idx = tid; idx < (S + 1) * r; idx += kThreads) sv[idx] = nd.lzv[idx];
+    // v_q(c), q <= S: for r <= 64 one register per slot, column c in lane c
+    // (read back with readlane: no staging barrier), else staged in LDS
+    constexpr bool kVL = RMAX <= 64;
+    __shared__ double sv[kVL ? 1 : kLz * RMAX];  // v_q(c) at q * r + c
+    T vl[kLz];
+    if constexpr (kVL) {
+      const int lane = threadIdx.x & 63;
+#pragma unroll
+      for (int q = 0; q < kLz; ++q) vl[q] = (q <= S) ? (T)nd.lzv[q * r + min(lane, r - 1)] : (T)0;
+    } else {
+      for (int idx = tid; idx < (S + 1) * r; idx += kThreads) sv[idx] = nd.lzv[idx];
+    }
+    auto vval = [&](int q, int c) -> T {
+      if constexpr (kVL) return lane_read(vl[q], c);
+      else return (T)sv[q * r + c];
+    };
     const GPtr<T> G = (GPtr<T>)nd.lzg;
     T gq[kLz - 1];
     int64_t iq[kLz - 1];
@@ -321,12 +335,12 @@ void k_pass(Node* nodes, unsigned long long* prof) {
       iq[q] = nd.lzi[q];
       kq[q] = nd.lzk[q];
     }
-    __syncthreads();
+    if constexpr (!kVL) __syncthreads();
     // the pending swaps applied to one element (row, c) of the working matrix
     auto replay = [&](T x, int c) {
 #pragma unroll
       for (int q = 0; q < kLz - 1; ++q)
-        if (q < S) x = (row == iq[q]) ? ((c == kq[q]) ? (T)1 : (T)0) : fma_t<T>(-gq[q], (T)sv[q * r + c], x);
+        if (q < S) x = (row == iq[q]) ? ((c == kq[q]) ? (T)1 : (T)0) : fma_t<T>(-gq[q], vval(q, c), x);
       return x;
     };
     const T g = replay(col_ld<T>(W + (int64_t)ks * m, ro), ks);
@@ -349,7 +363,7 @@ void k_pass(Node* nodes, unsigned long long* prof) {
         for (int u = 0; u < NR; ++u) {
           const int c = c0 + u;
           if (c < r) {
-            T b = fma_t<T>(-g, (T)sv[S * r + c], replay(bs[u], c));
+            T b = fma_t<T>(-g, vval(S, c), replay(bs[u], c));
             if (row == is) b = (c == ks) ? (T)1 : (T)0;
             if (valid) {
               if (wout) col_st<T>(W + (int64_t)c * m, ro, b);
