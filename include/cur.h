@@ -132,6 +132,10 @@ const char* cur_last_error(void);
  * algorithm (bit-identical arithmetic in every decision-relevant quantity).
  * The FP32 path streams the interpolation matrices in FP32 (fresh ones are
  * computed in FP64 from the FP32 input) with tau = 1e-4 by default.
+ * Workspace (grown on demand, kept by the context): per tree node, an m x |Jc|
+ * candidate panel, an m x max(|Jc|, r) working matrix and 4 m-element columns
+ * of pending row-swap history, in the input's element type, plus O(r^2)
+ * doubles (8192 x 8192 FP64 with r = 64: ~8.3 MiB per leaf, ~3 GiB in all).
  */
 cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
                       int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info);
