@@ -187,7 +187,7 @@ def main():
                     help="one untimed device copy of this size, the calibration of the byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding of the merge tree is a design note only)", file=sys.stderr)
         sys.exit(2)
 

@@ -121,7 +121,7 @@ const char* cur_last_error(void);
  * Selection (Def. 1 objective, Alg. 1 leaf start, Alg. 3 block partition,
  * binary merge tree).
  *   A      device, m x n, row-major, leading dimension lda >= n, dtype `dtype`
- *   r      1 <= r <= min(m, n) (r <= 128 in this build); one column of A
+ *   r      1 <= r <= min(m, n) and r <= 128; one column of A
  *          must be below 4 GiB (m x element size < 2^32), CUR_ERR_ARG otherwise
  *   opts   NULL for defaults
  *   I, J   device int64[r]: selected rows and columns, ascending.  On

@@ -52,7 +52,7 @@ static cur_status check_matrix(cur_dtype dtype, const void* A, int64_t m, int64_
   if (m < 1 || n < 1) return arg_error("m and n must be >= 1");
   if (lda < n) return arg_error("lda must be >= n");
   if (r < 1 || (int64_t)r > m || (int64_t)r > n) return arg_error("r must satisfy 1 <= r <= min(m, n)");
-  if (r > 128) return arg_error("r > 128 is not supported by this build");
+  if (r > 128) return arg_error("r > 128 is not supported (kernels are instantiated for r <= 128)");
   if (m > ((int64_t)1 << 40) || n > ((int64_t)1 << 40)) return arg_error("matrix dimensions too large");
   return CUR_OK;
 }
@@ -82,7 +82,7 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.max_swaps < 0) return arg_error("max_swaps must be >= 0");
   if (o.max_swaps == 0) o.max_swaps = 64 * r;
   if (o.prec < CUR_PREC_NATIVE || o.prec > CUR_PREC_FP8) return arg_error("prec out of range");
-  if (o.propose != 0) return arg_error("propose must be 0 in this build");
+  if (o.propose != 0) return arg_error("propose must be 0 (no learned proposal is implemented)");
   if (o.groups < 0 || o.groups > 3) return arg_error("groups must be 0 (autotuned) or 1..3");
   if (o.method != 0 && o.method != 1) return arg_error("method must be 0 (maximal volume) or 1 (norm-greedy)");
   if (o.method == 1 && o.trace) return arg_error("trace is not available for the norm-greedy method");
