@@ -90,8 +90,10 @@ typedef struct {
   int32_t method;      /* 0: maximal-volume tree (Alg. 1 leaves, swap loops, binary merge);
                           1: norm-greedy rows and columns (Alg. 2 with Alg. 3): r times the
                           row (column) of largest norm, projected out of all rows (columns);
-                          col_block, tau, max_swaps, groups and trace do not apply, info->logvol
-                          is NaN, and cur_select_batched rejects it                              */
+                          col_block, tau, max_swaps and groups do not apply, info->logvol is
+                          NaN, cur_select_batched rejects it, and a trace (capacity >= 1)
+                          receives one record whose I and J list the rows and columns in the
+                          order chosen (q = rank reached, short = 1 if below r)               */
   int32_t reserved1;
 } cur_opts;
 
@@ -108,9 +110,11 @@ typedef struct {
 void cur_opts_init(cur_opts* opts);
 
 /* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is
- * used for all work; NULL means the device's default (null) stream, so work is
- * ordered with everything else issued there.  The context owns a device
- * workspace that grows on demand. */
+ * used for all work; NULL means the device's default (null) stream, as a NULL
+ * hipStream_t does in every HIP call, so work is ordered with everything else
+ * issued there (PyTorch's default stream is that null stream).  A caller that
+ * wants the library on a private stream creates one and passes it.  The
+ * context owns a device workspace that grows on demand. */
 cur_status cur_create(cur_ctx* out, int device, void* hip_stream);
 cur_status cur_destroy(cur_ctx ctx);
 const char* cur_strerror(cur_status s);
@@ -120,6 +124,8 @@ const char* cur_last_error(void);
 /*
  * Selection (Def. 1 objective, Alg. 1 leaf start, Alg. 3 block partition,
  * binary merge tree).
+ *   dtype  a cur_dtype value (passed as int32_t so that any integer a caller
+ *          passes is a valid argument; others are CUR_ERR_ARG)
  *   A      device, m x n, row-major, leading dimension lda >= n, dtype `dtype`
  *   r      1 <= r <= min(m, n) and r <= 128; one column of A
  *          must be below 4 GiB (m x element size < 2^32), CUR_ERR_ARG otherwise
@@ -137,7 +143,7 @@ const char* cur_last_error(void);
  * of pending row-swap history, in the input's element type, plus O(r^2)
  * doubles (8192 x 8192 FP64 with r = 64: ~8.3 MiB per leaf, ~3 GiB in all).
  */
-cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+cur_status cur_select(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda,
                       int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info);
 
 /*
@@ -147,7 +153,7 @@ cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, in
  * r 2^-52, the pseudo-inverse from a one-sided Jacobi SVD with singular values
  * below r 2^-52 sigma_max dropped.  I, J: device int64[r], each in range.
  */
-cur_status cur_assemble(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+cur_status cur_assemble(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda,
                         int32_t r, const int64_t* I, const int64_t* J, void* C, double* U, void* R);
 
 /*
@@ -157,8 +163,10 @@ cur_status cur_assemble(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, 
  *   fro_rel  host, nullable: ||E||_F / ||A||_F
  *   prec     cur_prec of the GEMM (NATIVE for FP64 input; NATIVE, BF16X3 or
  *            FP8 for FP32 input).  U is always FP64; C U is formed in FP64.
+ * Returns CUR_ERR_NONFINITE (with *cheb NaN or infinite) when some entry of
+ * A - C U R is NaN or infinite, e.g. from a non-finite input.
  */
-cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+cur_status cur_residual(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda,
                         int32_t r, const void* C, const double* U, const void* R, int32_t prec,
                         double* cheb, double* fro_rel);
 

@@ -782,13 +782,15 @@ int oracle_cur_assemble(const double* A, int64_t m, int64_t n, int64_t lda, int 
  *   Bm = C * U (m x r; sums over l ascending),
  *   E(i,j) = A(i,j) - sum_k Bm(i,k) R(k,j) (k ascending),
  *   cheb = max |E(i,j)|, fro_rel = ||E||_F / ||A||_F.
- * C is m x r, U r x r, R r x n, all row-major FP64.
+ * C is m x r, U r x r, R r x n, all row-major FP64.  If some E(i,j) is NaN or
+ * infinite, cheb is NaN and the status ORC_ERR_NONFINITE.
  */
 int oracle_cur_residual(const double* A, int64_t m, int64_t n, int64_t lda, int r, const double* C,
                         const double* U, const double* R, double* cheb, double* fro_rel) {
   if (!A || !C || !U || !R || !cheb || m < 1 || n < 1 || lda < n || r < 1) return ORC_ERR_ARG;
   double* Bm = (double*)malloc(sizeof(double) * (size_t)r);
   double emax = 0.0, esq = 0.0, asq = 0.0;
+  int nonfinite = 0;
   for (int64_t i = 0; i < m; ++i) {
     for (int k = 0; k < r; ++k) {
       double s = 0.0;
@@ -800,15 +802,16 @@ int oracle_cur_residual(const double* A, int64_t m, int64_t n, int64_t lda, int 
       for (int k = 0; k < r; ++k) s = fma(Bm[k], R[(int64_t)k * n + j], s);
       double a = A[i * lda + j];
       double e = a - s;
-      if (fabs(e) > emax) emax = fabs(e);
+      if (!isfinite(e)) nonfinite = 1;
+      else if (fabs(e) > emax) emax = fabs(e);
       esq = fma(e, e, esq);
       asq = fma(a, a, asq);
     }
   }
   free(Bm);
-  *cheb = emax;
+  *cheb = nonfinite ? NAN : emax;
   if (fro_rel) *fro_rel = (asq > 0.0) ? sqrt(esq) / sqrt(asq) : 0.0;
-  return ORC_OK;
+  return nonfinite ? ORC_ERR_NONFINITE : ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -828,31 +831,28 @@ int oracle_cur_residual(const double* A, int64_t m, int64_t n, int64_t lda, int 
  * Alg. 3 only distributes the argmax and the update; it does not change the
  * result, so the oracle works on the whole matrix.
  *
- * Every sum over a vector (dot products, squared norms) is taken in one fixed
- * order: 64 partial sums, partial l accumulating the elements i = l, l + 64,
- * ... in ascending order with fma, then combined pairwise by a xor butterfly
- * (distances 32, 16, 8, 4, 2, 1).  The update of an element is one fma with
- * the coefficient c = (s . v) / (s . s).
+ * Sums over a vector (dot products, squared norms) run over the elements in
+ * ascending index order, one fma per element, as the definition reads.  The
+ * update of an element is one fma with the coefficient c = (s . v) / (s . s).
  */
-static double lane_sum_dot(const double* a, const double* b, int64_t len) {
-  double p[64], q[64];
-  for (int l = 0; l < 64; ++l) p[l] = 0.0;
-  for (int64_t i = 0; i < len; ++i) p[i & 63] = fma(a[i], b[i], p[i & 63]);
-  for (int d = 32; d >= 1; d >>= 1) {
-    for (int l = 0; l < 64; ++l) q[l] = p[l] + p[l ^ d];
-    for (int l = 0; l < 64; ++l) p[l] = q[l];
-  }
-  return p[0];
+static double plain_dot(const double* a, const double* b, int64_t len) {
+  double s = 0.0;
+  for (int64_t i = 0; i < len; ++i) s = fma(a[i], b[i], s);
+  return s;
 }
 
 /* Vectors W[v * len + i] (cnt of them, contiguous); order[t] receives the
- * chosen vector of step t.  Returns the number chosen (<= r). */
-static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* order) {
+ * chosen vector of step t.  If gap is non-NULL, gap[t] receives the margin of
+ * step t's choice, (best - runner-up) / (largest initial squared norm), the
+ * runner-up being the second largest squared norm among the candidates of
+ * that step (+inf when there is none); entries past the last step are left
+ * alone.  Returns the number chosen (<= r). */
+static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* order, double* gap) {
   double* nrm = (double*)malloc(sizeof(double) * (size_t)cnt);
   char* sel = (char*)calloc((size_t)cnt, 1);
   double nmax0 = 0.0;
   for (int64_t v = 0; v < cnt; ++v) {
-    nrm[v] = lane_sum_dot(W + v * len, W + v * len, len);
+    nrm[v] = plain_dot(W + v * len, W + v * len, len);
     if (nrm[v] > nmax0) nmax0 = nrm[v];
   }
   const double eps = (double)(len > cnt ? len : cnt) * ldexp(1.0, -52);
@@ -860,13 +860,19 @@ static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* orde
   int t = 0;
   for (; t < r; ++t) {
     int64_t j = -1;
-    double best = -1.0;
-    for (int64_t v = 0; v < cnt; ++v)
-      if (!sel[v] && nrm[v] > best) {
+    double best = -1.0, second = -1.0;
+    for (int64_t v = 0; v < cnt; ++v) {
+      if (sel[v]) continue;
+      if (nrm[v] > best) {
+        second = best;
         best = nrm[v];
         j = v;
+      } else if (nrm[v] > second) {
+        second = nrm[v];
       }
+    }
     if (j < 0 || !(best > theta)) break;
+    if (gap) gap[t] = second < 0.0 ? INFINITY : (best - second) / nmax0;
     sel[j] = 1;
     order[t] = j;
     const double* s = W + j * len;
@@ -874,9 +880,9 @@ static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* orde
     for (int64_t v = 0; v < cnt; ++v) {
       if (sel[v]) continue;
       double* w = W + v * len;
-      const double c = lane_sum_dot(s, w, len) / ss;
+      const double c = plain_dot(s, w, len) / ss;
       for (int64_t i = 0; i < len; ++i) w[i] = fma(-c, s[i], w[i]);
-      nrm[v] = lane_sum_dot(w, w, len);
+      nrm[v] = plain_dot(w, w, len);
     }
   }
   free(nrm);
@@ -889,21 +895,23 @@ static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* orde
  * norm-greedy rule.  A is m x n row-major (lda).  order_I / order_J (r each)
  * receive the choice order, I and J the same indices ascending; entries past
  * the rank reached are -1.  Returns ORC_OK, or ORC_ERR_RANK when either axis
- * stops short (*rank_rows / *rank_cols say where).
+ * stops short (*rank_rows / *rank_cols say where).  gap_I / gap_J (nullable,
+ * r doubles each) receive each step's margin as described at greedy_axis.
  */
 int oracle_greedy_select(const double* A, int64_t m, int64_t n, int64_t lda, int r, int64_t* order_I,
-                         int64_t* order_J, int64_t* I, int64_t* J, int* rank_rows, int* rank_cols) {
+                         int64_t* order_J, int64_t* I, int64_t* J, int* rank_rows, int* rank_cols,
+                         double* gap_I, double* gap_J) {
   if (!A || m < 1 || n < 1 || lda < n || r < 1 || r > m || r > n) return ORC_ERR_ARG;
   double* W = (double*)malloc(sizeof(double) * (size_t)(m * n));
   if (!W) return ORC_ERR_NOMEM;
   for (int64_t i = 0; i < r; ++i) order_I[i] = order_J[i] = I[i] = J[i] = -1;
   /* rows: vector i = A(i, :) */
   for (int64_t i = 0; i < m; ++i) memcpy(W + i * n, A + i * lda, sizeof(double) * (size_t)n);
-  const int qr = greedy_axis(W, n, m, r, order_I);
+  const int qr = greedy_axis(W, n, m, r, order_I, gap_I);
   /* columns: vector j = A(:, j) */
   for (int64_t i = 0; i < m; ++i)
     for (int64_t j = 0; j < n; ++j) W[j * m + i] = A[i * lda + j];
-  const int qc = greedy_axis(W, m, n, r, order_J);
+  const int qc = greedy_axis(W, m, n, r, order_J, gap_J);
   free(W);
   for (int t = 0; t < qr; ++t) I[t] = order_I[t];
   for (int t = 0; t < qc; ++t) J[t] = order_J[t];

@@ -76,7 +76,7 @@ def lib():
         L.oracle_cur_assemble.restype = i32
         L.oracle_cur_residual.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P]
         L.oracle_cur_residual.restype = i32
-        L.oracle_greedy_select.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P, P]
+        L.oracle_greedy_select.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P, P, P, P]
         L.oracle_greedy_select.restype = i32
         _lib = L
     return _lib
@@ -241,6 +241,19 @@ def residual(A, C, U, R):
     return cheb.value, fro.value
 
 
+def residual_raw(A, C, U, R):
+    """(status, cheb, fro_rel) without raising: status ERR_NONFINITE (and cheb
+    NaN) when A - C U R has a non-finite entry."""
+    A = _f64(A)
+    C, U, R = _f64(C), _f64(U), _f64(R)
+    m, n = A.shape
+    cheb = ctypes.c_double()
+    fro = ctypes.c_double()
+    rc = lib().oracle_cur_residual(_p(A), m, n, n, U.shape[0], _p(C), _p(U), _p(R), ctypes.byref(cheb),
+                                   ctypes.byref(fro))
+    return rc, cheb.value, fro.value
+
+
 def select_raw(A, r, w=0, tau=0.0, max_swaps=0):
     """Status code only (for the error-path tests); A may be any float64 array."""
     A = _f64(A)
@@ -255,7 +268,9 @@ def select_raw(A, r, w=0, tau=0.0, max_swaps=0):
 
 def greedy(A, r):
     """Norm-greedy selection of rows and columns (Alg. 2 with Alg. 3), see
-    oracle_greedy_select: choice orders, ascending I and J, status, ranks."""
+    oracle_greedy_select: choice orders, ascending I and J, status, ranks, and
+    each step's margin (best - runner-up squared norm) / (largest initial
+    squared norm) as gap_I / gap_J (NaN past the rank reached)."""
     A = _f64(A)
     m, n = A.shape
     oI = np.full(r, -1, np.int64)
@@ -264,9 +279,11 @@ def greedy(A, r):
     J = np.full(r, -1, np.int64)
     qr = ctypes.c_int(0)
     qc = ctypes.c_int(0)
+    gI = np.full(r, np.nan)
+    gJ = np.full(r, np.nan)
     st = lib().oracle_greedy_select(_p(A), m, n, n, r, _p(oI), _p(oJ), _p(I), _p(J), ctypes.byref(qr),
-                                    ctypes.byref(qc))
+                                    ctypes.byref(qc), _p(gI), _p(gJ))
     if st == ERR_ARG:
         raise ValueError("oracle_greedy_select: invalid argument")
     return {"order_I": oI, "order_J": oJ, "I": I, "J": J, "status": st, "rank_rows": qr.value,
-            "rank_cols": qc.value}
+            "rank_cols": qc.value, "gap_I": gI, "gap_J": gJ}

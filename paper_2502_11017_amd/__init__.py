@@ -210,7 +210,7 @@ def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, 
         import numpy as np
 
         w = col_block if col_block else max(64, r)
-        N = tree_size(n, max(w, 1))
+        N = 1 if method == METHOD_GREEDY else tree_size(n, max(w, 1))
         host = {"meta": np.zeros((N, 10), dtype=np.int64), "vol_m": np.zeros(N),
                 "I": np.zeros((N, r), dtype=np.int64), "J": np.zeros((N, r), dtype=np.int64)}
         tr = Trace(N, 0, host["meta"].ctypes.data, host["vol_m"].ctypes.data,

@@ -7,6 +7,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -26,24 +27,36 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
 def build(verbose: bool = False, jobs: int = 4) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    procs, objs = [], []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        while len([p for _, p in procs if p.poll() is None]) >= jobs:
-            procs[0][1].wait() if procs[0][1].poll() is None else None
-            break
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
     failed = []
-    for src, p in procs:
-        out, _ = p.communicate()
+
+    def finish(src, p, log):
+        p.wait()
+        log.seek(0)
+        out = log.read()
+        log.close()
         if p.returncode != 0:
             failed.append((src, out.decode(errors="replace")))
         elif verbose and out:
             sys.stdout.write(out.decode(errors="replace"))
+
+    running = []  # at most `jobs` compilers at a time, each drained when it ends
+    for src, obj in zip(SOURCES, objs):
+        while len(running) >= jobs:
+            done = [sp for sp in running if sp[1].poll() is not None]
+            if not done:
+                running[0][1].wait()
+                continue
+            for sp in done:
+                finish(*sp)
+                running.remove(sp)
+        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        log = tempfile.TemporaryFile()  # a file, not a pipe: a chatty compiler cannot block on it
+        running.append((src, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
+    for sp in running:
+        finish(*sp)
     if failed:
         for src, out in failed:
             sys.stderr.write(f"--- {src}\n{out}\n")

@@ -46,7 +46,7 @@ static cur_status arg_error(const std::string& msg) {
   return CUR_ERR_ARG;
 }
 
-static cur_status check_matrix(cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r) {
+static cur_status check_matrix(int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r) {
   if (dtype != CUR_F64 && dtype != CUR_F32) return arg_error("dtype must be CUR_F64 or CUR_F32");
   if (!A) return arg_error("A is NULL");
   if (m < 1 || n < 1) return arg_error("m and n must be >= 1");
@@ -85,7 +85,6 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.propose != 0) return arg_error("propose must be 0 (no learned proposal is implemented)");
   if (o.groups < 0 || o.groups > 3) return arg_error("groups must be 0 (autotuned) or 1..3");
   if (o.method != 0 && o.method != 1) return arg_error("method must be 0 (maximal volume) or 1 (norm-greedy)");
-  if (o.method == 1 && o.trace) return arg_error("trace is not available for the norm-greedy method");
   if (o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
   if (o.trace) {
     int64_t b = n / o.col_block;
@@ -96,6 +95,7 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
       if (c <= 1) break;
       c = (c + 1) / 2;
     }
+    if (o.method == 1) tot = 1;  // one record: the choice orders
     if (!o.trace->meta || !o.trace->vol_mant || !o.trace->I || !o.trace->J)
       return arg_error("cur_trace arrays must be non-NULL");
     if (o.trace->capacity < tot) return arg_error("cur_trace.capacity too small for the tree");
@@ -196,10 +196,11 @@ cur_status cur_destroy(cur_ctx ctx) {
   return CUR_OK;
 }
 
-cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+cur_status cur_select(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda,
                       int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info) {
-  cur_status st = check_matrix(dtype, A, m, n, lda, r);
+  cur_status st = check_matrix(dtype_in, A, m, n, lda, r);
   if (st != CUR_OK) return st;
+  const cur_dtype dtype = (cur_dtype)dtype_in;  // a valid enumerator from here on
   st = check_select_rows(dtype, m);
   if (st != CUR_OK) return st;
   if (!I || !J) return arg_error("I and J must be non-NULL device pointers");
@@ -209,14 +210,15 @@ cur_status cur_select(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, in
   if (!ctx) return arg_error("ctx is NULL");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
-  if (o.method == 1) return greedy_dispatch(ctx, dtype, A, m, n, lda, r, I, J, info);
+  if (o.method == 1) return greedy_dispatch(ctx, dtype, A, m, n, lda, r, I, J, info, o.trace);
   return select_dispatch(ctx, dtype, A, m, n, lda, r, o, I, J, info);
 }
 
-cur_status cur_assemble(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+cur_status cur_assemble(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda,
                         int32_t r, const int64_t* I, const int64_t* J, void* C, double* U, void* R) {
-  cur_status st = check_matrix(dtype, A, m, n, lda, r);
+  cur_status st = check_matrix(dtype_in, A, m, n, lda, r);
   if (st != CUR_OK) return st;
+  const cur_dtype dtype = (cur_dtype)dtype_in;
   if (!I || !J || !C || !U || !R) return arg_error("I, J, C, U and R must be non-NULL device pointers");
   if (!ctx) return arg_error("ctx is NULL");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
@@ -231,11 +233,12 @@ cur_status cur_assemble(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, 
   return assemble_dispatch(ctx, dtype, A, m, n, lda, r, I, J, C, U, R);
 }
 
-cur_status cur_residual(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+cur_status cur_residual(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda,
                         int32_t r, const void* C, const double* U, const void* R, int32_t prec,
                         double* cheb, double* fro_rel) {
-  cur_status st = check_matrix(dtype, A, m, n, lda, r);
+  cur_status st = check_matrix(dtype_in, A, m, n, lda, r);
   if (st != CUR_OK) return st;
+  const cur_dtype dtype = (cur_dtype)dtype_in;
   if (!C || !U || !R) return arg_error("C, U and R must be non-NULL device pointers");
   if (!cheb) return arg_error("cheb must be a non-NULL host pointer");
   if (prec < CUR_PREC_NATIVE || prec > CUR_PREC_FP8) return arg_error("prec out of range");
@@ -306,7 +309,7 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
     return arg_error("batched selection supports the maximal-volume method only");
   for (int32_t i = 0; i < count; ++i) {
     const cur_item& it = items[i];
-    cur_status st = check_matrix((cur_dtype)it.dtype, it.A, it.m, it.n, it.lda, it.r);
+    cur_status st = check_matrix(it.dtype, it.A, it.m, it.n, it.lda, it.r);
     if (st == CUR_OK) st = check_select_rows((cur_dtype)it.dtype, it.m);
     if (st != CUR_OK) return arg_error("item " + std::to_string(i) + ": " + last_error());
     if (!it.I || !it.J) return arg_error("item " + std::to_string(i) + ": I and J must be non-NULL");

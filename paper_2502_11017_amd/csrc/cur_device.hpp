@@ -24,6 +24,10 @@ struct Cand {
   int32_t pos;
 };
 
+// Maximum that keeps a NaN: once either operand is NaN the result is NaN
+// (fmax would drop it), so a non-finite residual entry reaches the caller.
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
 __device__ __forceinline__ Cand cand_none() {
   Cand c;
   c.val = -1.0;

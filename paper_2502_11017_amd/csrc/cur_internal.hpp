@@ -170,7 +170,7 @@ int tune_best(const TuneEntry& e);  // fastest group count of an explored entry
 cur_status ensure_groups(cur_ctx ctx);  // group streams and events of the context (select.hip)
 // Norm-greedy selection of rows and columns (greedy.hip).
 cur_status greedy_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda, int r,
-                           int64_t* I, int64_t* J, cur_info* info);
+                           int64_t* I, int64_t* J, cur_info* info, cur_trace* trace);
 void fresh_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 void pass_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 

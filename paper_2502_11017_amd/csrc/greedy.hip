@@ -5,10 +5,12 @@
 // an argmax launch over all candidates and an update launch with one
 // wavefront per vector.
 //
-// Every sum over a vector (dot products, squared norms) is taken in one fixed
-// order, which the reference implementation shares: lane l of the vector's
-// wavefront accumulates elements i = l, l + 64, ... ascending with fma, then
-// the 64 partials are combined by a xor butterfly (distances 32 .. 1).  Each
+// Every sum over a vector (dot products, squared norms) is split over one
+// wavefront: lane l accumulates elements i = l, l + 64, ... ascending with
+// fma, then the 64 partials are combined by a xor butterfly (distances
+// 32 .. 1).  That order differs from a plain ascending sum by rounding only, so
+// a choice can differ from one made with plain sums only where the two best
+// squared norms of a step lie within that rounding of each other.  Each
 // element update is one fma with the coefficient (s.v) / (s.s).  Norms are
 // compared squared; a chosen vector is no candidate again and is not updated;
 // the axis stops, rank-short, once the largest remaining squared norm is at
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_gr_update(double* __restrict__ W, 
 
 template <typename T>
 static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r, int64_t* I,
-                              int64_t* J, cur_info* info) {
+                              int64_t* J, cur_info* info, cur_trace* trace) {
   cur_status st = ensure_groups(ctx);
   if (st != CUR_OK) return st;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -241,6 +243,18 @@ static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
     info->rank = std::min(qr, qc);
     info->logvol = std::nan("");
   }
+  if (trace) {  // one record: rows and columns in the order chosen
+    int64_t* mt = trace->meta;
+    for (int f = 0; f < kMetaFields; ++f) mt[f] = 0;
+    mt[2] = std::min(qr, qc);
+    mt[3] = (qr < r || qc < r) ? 1 : 0;
+    trace->vol_mant[0] = 0.0;
+    for (int t = 0; t < r; ++t) {
+      trace->I[t] = t < qr ? hr[t] : -1;
+      trace->J[t] = t < qc ? hc[t] : -1;
+    }
+    trace->count = 1;
+  }
   if (qr < r || qc < r) {
     set_error("fewer than r vectors above the rank threshold");
     return CUR_ERR_RANK;
@@ -249,9 +263,9 @@ static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
 }
 
 cur_status greedy_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda, int r,
-                           int64_t* I, int64_t* J, cur_info* info) {
-  if (dtype == CUR_F64) return greedy_impl<double>(ctx, (const double*)A, m, n, lda, r, I, J, info);
-  return greedy_impl<float>(ctx, (const float*)A, m, n, lda, r, I, J, info);
+                           int64_t* I, int64_t* J, cur_info* info, cur_trace* trace) {
+  if (dtype == CUR_F64) return greedy_impl<double>(ctx, (const double*)A, m, n, lda, r, I, J, info, trace);
+  return greedy_impl<float>(ctx, (const float*)A, m, n, lda, r, I, J, info, trace);
 }
 
 }  // namespace cur

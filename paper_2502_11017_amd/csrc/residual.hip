@@ -101,14 +101,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
       for (int v = 0; v < 4; ++v) {
         const double av = pa[j][v];
         const double e = av - acc[i][j][v];
-        emax = fmax(emax, fabs(e));
+        emax = nan_max(emax, fabs(e));
         esq = fma(e, e, esq);
         asq = fma(av, av, asq);
       }
   }
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
-    emax = fmax(emax, __shfl_xor(emax, s, 64));
+    emax = nan_max(emax, __shfl_xor(emax, s, 64));
     esq += __shfl_xor(esq, s, 64);
     asq += __shfl_xor(asq, s, 64);
   }
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
   __syncthreads();
   if (tid == 0) {
     for (int q = 1; q < kThreads / 64; ++q) {
-      emax = fmax(emax, L.red[0][q]);
+      emax = nan_max(emax, L.red[0][q]);
       esq += L.red[1][q];
       asq += L.red[2][q];
     }
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C
 __global__ __launch_bounds__(kThreads) void k_resid_final(const double* part, int64_t nb, double* out) {
   double emax = 0.0, esq = 0.0, asq = 0.0;
   for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
-    emax = fmax(emax, part[3 * b]);
+    emax = nan_max(emax, part[3 * b]);
     esq += part[3 * b + 1];
     asq += part[3 * b + 2];
   }
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_final(const double* part, in
   __syncthreads();
   for (int w = kThreads / 2; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+      s[0][threadIdx.x] = nan_max(s[0][threadIdx.x], s[0][threadIdx.x + w]);
       s[1][threadIdx.x] += s[1][threadIdx.x + w];
       s[2][threadIdx.x] += s[2][threadIdx.x + w];
     }
@@ -266,6 +266,10 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   CUR_HIP_CHECK(hipStreamSynchronize(s));
   *cheb = h[0];
   if (fro_rel) *fro_rel = h[2] > 0.0 ? std::sqrt(h[1]) / std::sqrt(h[2]) : 0.0;
+  if (!std::isfinite(h[0])) {
+    set_error("A - C U R has a NaN or infinite entry");
+    return CUR_ERR_NONFINITE;
+  }
   return CUR_OK;
 }
 

@@ -251,14 +251,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mp(const float* __restric
         if constexpr (PREC == CUR_PREC_FP8) p = sa * bs[col] * (p + 0.0625f * acc2[i][j][v]);
         const double a = (double)av[i][v][j];
         const double e = a - (double)p;
-        emax = fmax(emax, fabs(e));
+        emax = nan_max(emax, fabs(e));
         esq = fma(e, e, esq);
         asq = fma(a, a, asq);
       }
     }
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
-    emax = fmax(emax, __shfl_xor(emax, s, 64));
+    emax = nan_max(emax, __shfl_xor(emax, s, 64));
     esq += __shfl_xor(esq, s, 64);
     asq += __shfl_xor(asq, s, 64);
   }
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mp(const float* __restric
   __syncthreads();
   if (tid == 0) {
     for (int q = 1; q < kThreads / 64; ++q) {
-      emax = fmax(emax, L.red[0][q]);
+      emax = nan_max(emax, L.red[0][q]);
       esq += L.red[1][q];
       asq += L.red[2][q];
     }

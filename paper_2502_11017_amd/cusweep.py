@@ -1,5 +1,5 @@
 """Strong scaling of one selection over compute units, after the scalability
-experiment of Sec. 4 (a 16384 x 16384 matrix, there over 2-64 processes).  On
+experiment of Sec. 3.2 (a 16384 x 16384 matrix, there over 2-64 processes).  On
 one GPU the resource that grows is the number of compute units the process
 may use; the ROCm runtime restricts every queue of a process to a set of them
 when HSA_CU_MASK is set before it starts, so each count runs in a child

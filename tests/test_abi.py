@@ -125,11 +125,11 @@ def test_tune_cache_argument_errors():
     assert L.cur_profile_enable(None, 1) == cur.ERR_ARG
 
 
-def test_greedy_method_rejects_trace_and_batching():
+def test_greedy_method_trace_needs_arrays_and_rejects_batching():
     o = cur.make_opts(method=1)
     tr = cur.Trace(1, 0, None, None, None, None)
     o.trace = ctypes.pointer(tr)
-    assert _sel(opts=o) == cur.ERR_ARG and "trace" in cur.last_error()
+    assert _sel(opts=o) == cur.ERR_ARG and "cur_trace arrays" in cur.last_error()
     o = cur.make_opts(method=1)
     L = cur.lib()
     items = (cur.Item * 1)(cur.Item(cur.F64, 3, 1, 10, 12, 12, 1, 1))

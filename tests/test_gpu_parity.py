@@ -22,7 +22,11 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 import paper_2502_11017_amd as cur  # noqa: E402
 from paper_2502_11017_amd import workloads as W  # noqa: E402
-from tests.helpers import row_interp  # noqa: E402
+import os  # noqa: E402
+
+from tests.helpers import check_tree_golden, greedy_first_near_tie, read_tree_golden, row_interp  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 DEV = torch.device("cuda:0")
 
@@ -223,6 +227,24 @@ def test_residual_ragged(orc, m, n, r):
     assert abs(fro - ofro) <= 1e-10
 
 
+@pytest.mark.parametrize("dt,prec", [(torch.float64, cur.PREC_NATIVE), (torch.float32, cur.PREC_NATIVE),
+                                     (torch.float32, cur.PREC_BF16X3), (torch.float32, cur.PREC_FP8)])
+def test_residual_nonfinite_is_reported(orc, dt, prec):
+    """A NaN in A reaches the residual's maximum (no NaN-dropping max): the call
+    returns ERR_NONFINITE, as the oracle does."""
+    Ah = W.gaussian(300, 200, 12)
+    I, J = np.array([3, 50, 99, 200]), np.array([1, 17, 150, 199])
+    A = torch.from_numpy(Ah).to(dt).to(DEV)
+    say(f"case residual nonfinite {dt} prec={prec}")
+    C, U, R = cur.assemble(A, torch.from_numpy(I).to(DEV), torch.from_numpy(J).to(DEV))
+    A[250, 100] = float("nan")
+    with pytest.raises(cur.CurError) as ei:
+        cur.residual(A, C, U, R, prec)
+    assert ei.value.status == cur.ERR_NONFINITE
+    rc, _, _ = orc.residual_raw(A.cpu().numpy(), C.cpu().numpy(), U.cpu().numpy(), R.cpu().numpy())
+    assert rc == orc.ERR_NONFINITE
+
+
 def test_select_batched_matches_single(orc):
     say("case batched")
     As = [torch.from_numpy(W.gaussian(m, n, s)).to(DEV) for (m, n, s) in [(300, 200, 1), (128, 500, 2), (700, 64, 3)]]
@@ -344,17 +366,40 @@ GREEDY_CASES = [
 ]
 
 
-@pytest.mark.parametrize("m,n,r,seed,dt", GREEDY_CASES)
-def test_greedy_matches_oracle(orc, m, n, r, seed, dt):
-    """Norm-greedy rows and columns (Alg. 2 with Alg. 3): same index sets and
-    status as the oracle, bit for bit (same sums in the same order)."""
-    A = torch.from_numpy(W.gaussian(m, n, seed)).to(dt).to(DEV)
-    say(f"case greedy m={m} n={n} r={r} seed={seed} {dt}")
-    g = cur.select(A, r, method=cur.METHOD_GREEDY)
+def greedy_both(orc, A, r):
+    """GPU and oracle norm-greedy selections with the GPU's choice orders."""
+    g = cur.select(A, r, method=cur.METHOD_GREEDY, trace=True)
     o = orc.greedy(A.cpu().numpy(), r)
+    return g, o
+
+
+def assert_greedy_agrees(g, o, m, n, r):
+    """The GPU sums a vector in lane-strided order, the oracle in plain
+    ascending order.  At every step whose margin (best - runner-up squared
+    norm) exceeds the rounding bound of helpers.greedy_margin_bound both must
+    choose the same vector; the comparison ends at the first near-tie, and the
+    test matrices are chosen so that none occurs (asserted)."""
+    tr = g["trace"]
+    gI, gJ = tr["I"][0], tr["J"][0]
+    for order, gaps, length, q in ((gI, o["gap_I"], n, o["rank_rows"]), (gJ, o["gap_J"], m, o["rank_cols"])):
+        stop = greedy_first_near_tie(gaps, q, length)
+        assert stop == q, f"near-tie at step {stop} of {q}: margin {gaps[stop]:.3e}"
+        ref = o["order_I"] if order is gI else o["order_J"]
+        np.testing.assert_array_equal(order[:q], ref[:q])
     assert g["status"] == o["status"]
     np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
     np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+
+
+@pytest.mark.parametrize("m,n,r,seed,dt", GREEDY_CASES)
+def test_greedy_matches_oracle(orc, m, n, r, seed, dt):
+    """Norm-greedy rows and columns (Alg. 2 with Alg. 3): the same choice at
+    every step whose margin exceeds the rounding bound (all steps here), so
+    the same index sets and status."""
+    A = torch.from_numpy(W.gaussian(m, n, seed)).to(dt).to(DEV)
+    say(f"case greedy m={m} n={n} r={r} seed={seed} {dt}")
+    g, o = greedy_both(orc, A, r)
+    assert_greedy_agrees(g, o, m, n, r)
     assert np.isnan(g["logvol"])
 
 
@@ -362,18 +407,13 @@ def test_greedy_rank_short_and_c2_recipe(orc):
     rng = np.random.default_rng(36)
     A = torch.from_numpy(rng.standard_normal((400, 6)) @ rng.standard_normal((6, 500))).to(DEV)
     say("case greedy rank-short")
-    g = cur.select(A, 10, method=cur.METHOD_GREEDY)
-    o = orc.greedy(A.cpu().numpy(), 10)
+    g, o = greedy_both(orc, A, 10)
     assert g["status"] == o["status"] == cur.ERR_RANK and g["rank"] == 6
-    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
-    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    assert_greedy_agrees(g, o, 400, 500, 10)
     A = W.c2(37, device=DEV, n=1024)
     say("case greedy c2-recipe n=1024 r=64")
-    g = cur.select(A, 64, method=cur.METHOD_GREEDY)
-    o = orc.greedy(A.cpu().numpy(), 64)
-    assert g["status"] == o["status"]
-    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
-    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    g, o = greedy_both(orc, A, 64)
+    assert_greedy_agrees(g, o, 1024, 1024, 64)
     B = A.clone()
     B[5, 9] = float("nan")
     with pytest.raises(cur.CurError) as ei:
@@ -391,3 +431,17 @@ def test_error_curve_points_decrease():
     for method in (cur.METHOD_MAXVOL, cur.METHOD_GREEDY):
         fros = [curves.point(A, r, method)[1] for r in (2, 4, 8)]
         assert fros[0] < 1.0 and fros[0] > fros[1] > fros[2], (method, fros)
+
+
+@pytest.mark.parametrize("case", read_tree_golden(os.path.join(GOLDEN, "tree_shape.txt")),
+                         ids=lambda c: c["name"])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_tree_shape_and_merge_tie_golden(case, dt):
+    """The hand-derived tree tables (5 and 12 leaves, merge tie to the left
+    child, two identical blocks) hold on the GPU too, in both dtypes (the
+    entries are small integers, exact in FP32)."""
+    say(f"case golden tree {case['name']} {dt}")
+    A = torch.from_numpy(case["A"]).to(dt).to(DEV)
+    g = cur.select(A, case["r"], col_block=case["w"], trace=True)
+    assert g["status"] == cur.OK
+    check_tree_golden(case, g["I"].cpu().numpy(), g["J"].cpu().numpy(), g["trace"], g["logvol"])

@@ -14,8 +14,9 @@ import numpy as np
 import pytest
 
 from paper_2502_11017_amd import workloads as W
-from tests.helpers import (EPS, brute_force_maxvol, col_interp, rand, root_candidates,
-                           row_interp, single_swap_gain, trace_logvol)
+from tests.helpers import (EPS, brute_force_maxvol, check_tree_golden, col_interp, rand,
+                           read_tree_golden, root_candidates, row_interp, single_swap_gain,
+                           trace_logvol)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -384,6 +385,26 @@ def test_nonfinite_input(orc, bad):
     assert rc == orc.ERR_NONFINITE
 
 
+@pytest.mark.parametrize("where", ["A", "R"])
+def test_nonfinite_residual_is_reported(orc, where):
+    """A NaN or infinity in A or in a factor makes some E(i,j) non-finite: the
+    residual reports ERR_NONFINITE with cheb NaN instead of a finite maximum
+    over the remaining entries."""
+    A = rand(30, 25, 11)
+    I, J = np.array([1, 4, 9]), np.array([0, 7, 20])
+    C, U, R, _ = orc.assemble(A, I, J)
+    if where == "A":
+        A = A.copy()
+        A[12, 5] = np.nan
+    else:
+        R = R.copy()
+        R[1, 3] = np.inf
+    rc, cheb, _ = orc.residual_raw(A, C, U, R)
+    assert rc == orc.ERR_NONFINITE and np.isnan(cheb)
+    rc, cheb, _ = orc.residual_raw(rand(30, 25, 11), *orc.assemble(rand(30, 25, 11), I, J)[:3])
+    assert rc == orc.OK and np.isfinite(cheb)
+
+
 def test_zero_matrix_is_rank_zero(orc):
     rc, info, _, _ = orc.select_raw(np.zeros((9, 9)), 2)
     assert rc == orc.ERR_RANK and info.rank == 0
@@ -394,3 +415,15 @@ def test_rank_deficient_reports_pivots_found(orc):
     rc, info, I, J = orc.select_raw(A, 4, w=16)
     assert rc == orc.ERR_RANK and info.rank == 2
     assert np.all(I[:2] >= 0) and np.all(I[2:] == -1)
+
+
+# ---------------------------------------------------------------- tree shape and merge tie rule
+@pytest.mark.parametrize("case", read_tree_golden(os.path.join(GOLDEN, "tree_shape.txt")),
+                         ids=lambda c: c["name"])
+def test_tree_shape_and_merge_tie_golden(orc, case):
+    """Hand-derived per-node (level, index, promoted, I, J) tables for 5 and 12
+    leaves (pairing (2p, 2p+1), odd last node promoted, merge tie to the left
+    child) and the two-identical-blocks case (tests/golden/tree_shape.txt)."""
+    o = orc.select(case["A"], case["r"], w=case["w"], trace=True)
+    assert o["status"] == orc.OK
+    check_tree_golden(case, o["I"], o["J"], o["trace"], o["logvol"])

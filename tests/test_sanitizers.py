@@ -1,0 +1,65 @@
+"""The CPU oracle and the library's host argument paths under AddressSanitizer
+and UndefinedBehaviorSanitizer (CPU only: the sanitizers instrument host code;
+no GPU code is built with them).
+
+- The oracle (plain C) is compiled with gcc -fsanitize=address,undefined
+  together with tests/sanitize/oracle_driver.c, which calls every exported
+  oracle function on small seeded inputs and on its error paths.
+- The library's C-ABI front end (api.hip) is compiled by hipcc with the
+  sanitizers on its host pass only (-Xarch_host), linked with the library's
+  other objects from the in-tree build and tests/sanitize/abi_driver.cpp,
+  which drives every argument error with a NULL context.
+Any sanitizer report fails the test (reports are made fatal).
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAN = os.path.join(ROOT, "tests", "sanitize")
+PKG = os.path.join(ROOT, "paper_2502_11017_amd")
+HIPCC = "/opt/rocm/bin/hipcc"
+CLANG = "/opt/rocm/llvm/bin/clang++"
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+           UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+
+
+def _run(exe):
+    p = subprocess.run([exe], capture_output=True, text=True, env=ENV, timeout=120)
+    out = p.stdout + p.stderr
+    assert p.returncode == 0 and "OK" in p.stdout, out
+    assert "runtime error" not in out and "AddressSanitizer" not in out, out
+
+
+def test_oracle_under_asan_ubsan(tmp_path):
+    exe = str(tmp_path / "oracle_san")
+    subprocess.check_call(["gcc", "-g", "-O1", "-std=c11", "-D_GNU_SOURCE", "-mfma", "-ffp-contract=off",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           os.path.join(SAN, "oracle_driver.c"), os.path.join(ROOT, "oracle", "cur_oracle.c"),
+                           "-lm", "-o", exe])
+    _run(exe)
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)), reason="ROCm toolchain missing")
+def test_abi_host_paths_under_asan_ubsan(tmp_path):
+    objdir = os.path.join(PKG, "_build")
+    others = [os.path.join(objdir, f"{s}.o") for s in ("select", "pass", "assemble", "residual", "residual_mp",
+                                                       "greedy")]
+    if not all(os.path.exists(o) for o in others):
+        pytest.skip("library objects not built (python -m paper_2502_11017_amd.build)")
+    api = str(tmp_path / "api_san.o")
+    flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Wno-unused-result", "-Wno-unused-value", "-I" + os.path.join(ROOT, "include")]
+    subprocess.run([HIPCC, *flags, "-c", os.path.join(PKG, "csrc", "api.hip"), "-o", api], check=True,
+                   capture_output=True)
+    exe = str(tmp_path / "abi_san")
+    subprocess.check_call([CLANG, "-g", "-O1", "-std=c++17", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(SAN, "abi_driver.cpp"), api, *others, "-L/opt/rocm/lib", "-lamdhip64",
+                           "-Wl,-rpath,/opt/rocm/lib", "-o", exe])
+    _run(exe)
