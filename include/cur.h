@@ -76,7 +76,7 @@ typedef struct {
 typedef struct {
   int32_t struct_size; /* sizeof(cur_opts), for ABI versioning                                   */
   int32_t col_block;   /* leaf column-block width w; 0 -> max(64, r); must be >= r               */
-  double tau;          /* a swap happens iff |B| > 1 + tau; 0 -> 1e-13 (F64) / 1e-4 (F32)        */
+  double tau;          /* a swap happens iff |B| > 1 + tau; 0 -> 1e-13                           */
   int32_t max_swaps;   /* swap budget per tree node; 0 -> 64 r                                   */
   int32_t prec;        /* cur_prec of the assembly/residual GEMMs (selection itself is exact)    */
   int32_t propose;     /* 0: no candidate proposal                                               */
@@ -127,8 +127,9 @@ const char* cur_last_error(void);
  *   dtype  a cur_dtype value (passed as int32_t so that any integer a caller
  *          passes is a valid argument; others are CUR_ERR_ARG)
  *   A      device, m x n, row-major, leading dimension lda >= n, dtype `dtype`
- *   r      1 <= r <= min(m, n) and r <= 128; one column of A
- *          must be below 4 GiB (m x element size < 2^32), CUR_ERR_ARG otherwise
+ *   r      1 <= r <= min(m, n) and r <= 128; m x 8 bytes must be below
+ *          4 GiB (the row kernels address one FP64 column with 32-bit
+ *          offsets), CUR_ERR_ARG otherwise
  *   opts   NULL for defaults
  *   I, J   device int64[r]: selected rows and columns, ascending.  On
  *          CUR_ERR_RANK the first info->rank entries hold the pivots found and
@@ -136,12 +137,15 @@ const char* cur_last_error(void);
  *   info   host, nullable
  * The FP64 path computes exactly the sequence of decisions of the documented
  * algorithm (bit-identical arithmetic in every decision-relevant quantity).
- * The FP32 path streams the interpolation matrices in FP32 (fresh ones are
- * computed in FP64 from the FP32 input) with tau = 1e-4 by default.
+ * FP32 input is widened exactly and the selection computes in FP64 (the
+ * candidate panels stay FP32), so it makes the decisions of the FP64 path on
+ * the widened values: the same result as the FP64 call on A converted to
+ * double.
  * Workspace (grown on demand, kept by the context): per tree node, an m x |Jc|
- * candidate panel, an m x max(|Jc|, r) working matrix and 4 m-element columns
- * of pending row-swap history, in the input's element type, plus O(r^2)
- * doubles (8192 x 8192 FP64 with r = 64: ~8.3 MiB per leaf, ~3 GiB in all).
+ * candidate panel in the input's element type, an FP64 working matrix of
+ * m x max(|Jc|, r) and 4 FP64 m-element columns of pending row-swap history,
+ * plus O(r^2) doubles (8192 x 8192 FP64 with r = 64: ~8.3 MiB per leaf,
+ * ~3 GiB in all).
  */
 cur_status cur_select(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda,
                       int32_t r, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info);

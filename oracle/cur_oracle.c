@@ -564,9 +564,32 @@ int oracle_tree_size(int64_t b) {
  * Optional trace (all four trace pointers non-null): one record per node of
  * every level, level by level, index ascending.
  */
+static int select_impl(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
+                       int max_swaps, double theta_rel, int64_t* I_out, int64_t* J_out, orc_info* info,
+                       int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ);
+
 int oracle_cur_select(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
                       int max_swaps, int64_t* I_out, int64_t* J_out, orc_info* info,
                       int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ) {
+  return select_impl(A, m, n, lda, r, w, tau, max_swaps, 0.0, I_out, J_out, info, tmeta, tvol, tI, tJ);
+}
+
+/*
+ * The same selection with the numerical-zero pivot threshold set to
+ * theta_rel * max|A| instead of max(m,n) 2^-52 max|A| (theta_rel > 0).  Used
+ * to check the rank verdicts of the GPU's FP32 path, whose threshold is
+ * r 2^-23 max|A| (the rounding of r FP32 elimination steps), on the exactly
+ * upcast matrix.
+ */
+int oracle_cur_select_theta(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
+                            int max_swaps, double theta_rel, int64_t* I_out, int64_t* J_out, orc_info* info) {
+  if (!(theta_rel > 0.0)) return ORC_ERR_ARG;
+  return select_impl(A, m, n, lda, r, w, tau, max_swaps, theta_rel, I_out, J_out, info, NULL, NULL, NULL, NULL);
+}
+
+static int select_impl(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
+                       int max_swaps, double theta_rel, int64_t* I_out, int64_t* J_out, orc_info* info,
+                       int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ) {
   if (info) memset(info, 0, sizeof(*info));
   if (!A || !I_out || !J_out || m < 1 || n < 1 || lda < n || r < 1 || (int64_t)r > m ||
       (int64_t)r > n || w < 0 || tau < 0.0 || max_swaps < 0)
@@ -588,7 +611,7 @@ int oracle_cur_select(const double* A, int64_t m, int64_t n, int64_t lda, int r,
     if (info) { info->rank = 0; info->status = ORC_ERR_RANK; }
     return ORC_ERR_RANK;
   }
-  const double theta = (double)(m > n ? m : n) * 0x1p-52 * amax;
+  const double theta = theta_rel > 0.0 ? theta_rel * amax : (double)(m > n ? m : n) * 0x1p-52 * amax;
 
   int64_t b = n / w;
   if (b < 1) b = 1;

@@ -66,6 +66,8 @@ def lib():
         L.oracle_tree_size.restype = i32
         L.oracle_cur_select.argtypes = [P, i64, i64, i64, i32, i32, dbl, i32, P, P, P, P, P, P, P]
         L.oracle_cur_select.restype = i32
+        L.oracle_cur_select_theta.argtypes = [P, i64, i64, i64, i32, i32, dbl, i32, dbl, P, P, P]
+        L.oracle_cur_select_theta.restype = i32
         L.oracle_sm_row_update.argtypes = [P, i64, i32, i64, i32, P]
         L.oracle_sm_row_update.restype = None
         L.oracle_sm_col_update.argtypes = [P, i32, i32, i32, i32, P, P]
@@ -183,6 +185,19 @@ def select(A, r, w=0, tau=0.0, max_swaps=0, trace=False):
     if trace and ww >= r:
         out["trace"] = {"meta": tm, "vol_m": tv, "I": tI, "J": tJ}
     return out
+
+
+def select_theta(A, r, theta_rel, w=0, tau=0.0, max_swaps=0):
+    """The selection with pivot threshold theta_rel * max|A| (see
+    oracle_cur_select_theta); dict with status, rank, I, J."""
+    A = _f64(A)
+    m, n = A.shape
+    I = np.full(r, -1, dtype=np.int64)
+    J = np.full(r, -1, dtype=np.int64)
+    info = _Info()
+    rc = lib().oracle_cur_select_theta(_p(A), m, n, n, r, int(w), float(tau), int(max_swaps), float(theta_rel),
+                                       _p(I), _p(J), ctypes.byref(info))
+    return {"status": rc, "I": I, "J": J, "rank": info.rank, "logvol": info.logvol}
 
 
 def sm_row_update(B, i, k):

@@ -58,10 +58,11 @@ static cur_status check_matrix(int32_t dtype, const void* A, int64_t m, int64_t 
 }
 
 // The selection's row kernels address a column of the working matrices with a
-// 32-bit byte offset: one column must stay below 4 GiB.
+// 32-bit byte offset: one column must stay below 4 GiB, in FP64 for either
+// input type (the elimination residual is FP64).
 static cur_status check_select_rows(cur_dtype dtype, int64_t m) {
-  const int64_t es = dtype == CUR_F64 ? 8 : 4;
-  if (m * es >= ((int64_t)1 << 32)) return arg_error("m x element size must be below 4 GiB for selection");
+  (void)dtype;
+  if (m * 8 >= ((int64_t)1 << 32)) return arg_error("m x 8 bytes must be below 4 GiB for selection");
   return CUR_OK;
 }
 
@@ -78,7 +79,8 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.col_block == 0) o.col_block = r > 64 ? r : 64;
   if (o.col_block < r) return arg_error("col_block must be >= r");
   if (!(o.tau >= 0.0)) return arg_error("tau must be >= 0");
-  if (o.tau == 0.0) o.tau = dtype == CUR_F64 ? 1e-13 : 1e-4;
+  if (o.tau == 0.0) o.tau = 1e-13;
+  (void)dtype;
   if (o.max_swaps < 0) return arg_error("max_swaps must be >= 0");
   if (o.max_swaps == 0) o.max_swaps = 64 * r;
   if (o.prec < CUR_PREC_NATIVE || o.prec > CUR_PREC_FP8) return arg_error("prec out of range");

@@ -55,7 +55,7 @@ struct Node {
   double tau;        // swap iff |B| > 1 + tau
   double theta;      // numerical-zero pivot threshold of ACA
   void* panel;       // m x ncmax, column-major (ld m), element T: A(:, Jc)
-  void* work;        // m x max(ncmax, r), column-major: ACA residual, then B
+  void* work;        // m x max(ncmax, r), column-major, FP64: ACA residual, then B
   double* X;         // r x r row-major: A(I,J)^{-1}
   double* Bc;        // r x ncmax row-major: column interpolation matrix
   double* vec;       // max(ncmax, r): pivot-row factors f (ACA) or v (row swap)
@@ -67,7 +67,7 @@ struct Node {
   int64_t* I;        // r: selected rows (current order)
   int32_t* Jp;       // r: selected candidate positions (current order)
   double* dbg;       // 4 x kDbgRing swap log (kind, index, slot, pivot) for diagnostics
-  void* lzg;         // kLz x m, column s (ld m), element T: the column g_s = B(:, k_s)
+  void* lzg;         // kLz x m, column s (ld m), FP64: the column g_s = B(:, k_s)
                      // before row swap s of the pending history
   double* lzv;       // kLz x r row-major: the factors v_s of those swaps
   const void* src;   // leaves: the matrix A this tree selects from (element T)

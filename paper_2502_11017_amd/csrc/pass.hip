@@ -199,23 +199,23 @@ void k_pass(Node* nodes, unsigned long long* prof) {
   using BF = std::integral_constant<bool, false>;
 
   if (st == ST_ACA) {
+    // The ACA residual is FP64 for either input type (FP32 input widens
+    // exactly), so the pivots, and with them the rank decisions, are those of
+    // FP64 elimination on the input, as in the FP64 path.
     const int t = nd.t, na = nd.na, nc = nd.nc;
     const int32_t* cmap = nd.colmap;
     const double* f = nd.vec;
-    const GPtr<const T> src = (t <= 1) ? P : (GPtr<const T>)W;
+    const GPtr<double> WA = (GPtr<double>)nd.work;
+    const uint32_t rowc = (uint32_t)(valid ? row : m - 1);
+    const uint32_t ro8 = rowc * 8u;  // byte offset of the row in an FP64 column
     const bool in_lanes = na <= kLaneCols;
     int idr[4];
-    T fr[4];
+    double fr[4];
     if (in_lanes) {
       lane_load(idr, cmap, na);
-      if (t > 0) {
-        double fd[4];
-        lane_load(fd, f, na);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fr[q] = (T)fd[q];
-      }
+      if (t > 0) lane_load(fr, f, na);
     }
-    AcaBest<T> ab;
+    AcaBest<double> ab;
     if (t == 0) {
       // first step: the argmax of the panel itself
       auto rounds = [&](auto lanes) {
@@ -224,7 +224,7 @@ void k_pass(Node* nodes, unsigned long long* prof) {
 #pragma unroll
           for (int u = 0; u < NR; ++u) {
             const int cc = min(c0 + u, na - 1);  // in range; extra lanes of the round are ignored
-            xs[u] = col_ld<T>(src + (int64_t)cc * m, ro);
+            xs[u] = col_ld<T>(P + (int64_t)cc * m, ro);
           }
           int idq = 0;
           if constexpr (decltype(lanes)::value) idq = lane_reg(idr, c0 >> 6);
@@ -235,7 +235,7 @@ void k_pass(Node* nodes, unsigned long long* prof) {
               int idu;
               if constexpr (decltype(lanes)::value) idu = lane_read(idq, c & 63);
               else idu = cmap[c];
-              if (valid) ab.take(xs[u], idu, c);
+              if (valid) ab.take((double)xs[u], idu, c);
             }
           }
         }
@@ -246,18 +246,22 @@ void k_pass(Node* nodes, unsigned long long* prof) {
       // R <- R - R(:, pc) f^T with row pi zeroed; the last active column moves
       // into the freed slot pc.  A later round only reads columns past the
       // earlier ones and writes those columns or pc, which was read already.
+      // The residual is read from the panel (input type) at t = 1, from the
+      // FP64 working matrix after that.
       const int pc = nd.pend_k;
       const int64_t pi = nd.pend_i;
-      auto rounds = [&](auto lanes) {
-        const T g = col_ld<T>(src + (int64_t)pc * m, ro);
+      auto rounds = [&](auto src, uint32_t rs, auto lanes) {
+        using E = std::remove_cv_t<std::remove_pointer_t<decltype(src)>>;
+        const GPtr<const E> S = (GPtr<const E>)src;
+        const double g = (double)col_ld<E>(S + (int64_t)pc * m, rs);
         for (int c0 = 0; c0 < na; c0 += NR) {
-          T xs[NR];
+          E xs[NR];
 #pragma unroll
           for (int u = 0; u < NR; ++u) {
             const int cc = min(c0 + u, na - 1);
-            xs[u] = col_ld<T>(src + (int64_t)cc * m, ro);
+            xs[u] = col_ld<E>(S + (int64_t)cc * m, rs);
           }
-          T fq = (T)0;
+          double fq = 0.0;
           int idq = 0;
           if constexpr (decltype(lanes)::value) {
             fq = lane_reg(fr, c0 >> 6);
@@ -269,28 +273,35 @@ void k_pass(Node* nodes, unsigned long long* prof) {
             if (c < na && c != pc) {
               // more than kLaneCols columns (a leaf block wider than 256): the
               // coefficients are read here, after the previous stores (slower)
-              T fcu;
+              double fcu;
               int idu;
               if constexpr (decltype(lanes)::value) {
                 fcu = lane_read(fq, c & 63);
                 idu = lane_read(idq, c & 63);
               } else {
-                fcu = (T)f[c];
+                fcu = f[c];
                 idu = cmap[c];
               }
-              T x = fma_t<T>(-g, fcu, xs[u]);
-              if (row == pi) x = (T)0;
+              double x = fma(-g, fcu, (double)xs[u]);
+              if (row == pi) x = 0.0;
               const int np = (c == na - 1) ? pc : c;
               if (valid) {
-                col_st<T>(W + (int64_t)np * m, ro, x);
+                col_st<double>(WA + (int64_t)np * m, ro8, x);
                 ab.take(x, idu, np);
               }
             }
           }
         }
       };
-      if (in_lanes) rounds(BT());
-      else rounds(BF());
+      const T* Pg = (const T*)nd.panel;
+      const double* Wg = (const double*)nd.work;
+      if (t == 1) {
+        if (in_lanes) rounds(Pg, ro, BT());
+        else rounds(Pg, ro, BF());
+      } else {
+        if (in_lanes) rounds(Wg, ro8, BT());
+        else rounds(Wg, ro8, BF());
+      }
     }
     ab.to_cand(best, row, nc);
   } else {
@@ -313,39 +324,41 @@ void k_pass(Node* nodes, unsigned long long* prof) {
     // (read back with readlane: no staging barrier), else staged in LDS
     constexpr bool kVL = RMAX <= 64;
     __shared__ double sv[kVL ? 1 : kLz * RMAX];  // v_q(c) at q * r + c
-    T vl[kLz];
+    double vl[kLz];
     if constexpr (kVL) {
       const int lane = threadIdx.x & 63;
 #pragma unroll
-      for (int q = 0; q < kLz; ++q) vl[q] = (q <= S) ? (T)nd.lzv[q * r + min(lane, r - 1)] : (T)0;
+      for (int q = 0; q < kLz; ++q) vl[q] = (q <= S) ? nd.lzv[q * r + min(lane, r - 1)] : 0.0;
     } else {
       for (int idx = tid; idx < (S + 1) * r; idx += kThreads) sv[idx] = nd.lzv[idx];
     }
-    auto vval = [&](int q, int c) -> T {
+    auto vval = [&](int q, int c) -> double {
       if constexpr (kVL) return lane_read(vl[q], c);
-      else return (T)sv[q * r + c];
+      else return sv[q * r + c];
     };
-    const GPtr<T> G = (GPtr<T>)nd.lzg;
-    T gq[kLz - 1];
+    const GPtr<double> G = (GPtr<double>)nd.lzg;
+    const GPtr<double> WB = (GPtr<double>)nd.work;
+    const uint32_t ro8 = (uint32_t)(valid ? row : m - 1) * 8u;
+    double gq[kLz - 1];
     int64_t iq[kLz - 1];
     int kq[kLz - 1];
 #pragma unroll
     for (int q = 0; q < kLz - 1; ++q) {
-      gq[q] = (q < S) ? col_ld<T>(G + (int64_t)q * m, ro) : (T)0;
+      gq[q] = (q < S) ? col_ld<double>(G + (int64_t)q * m, ro8) : 0.0;
       iq[q] = nd.lzi[q];
       kq[q] = nd.lzk[q];
     }
     if constexpr (!kVL) __syncthreads();
     // the pending swaps applied to one element (row, c) of the working matrix
-    auto replay = [&](T x, int c) {
+    auto replay = [&](double x, int c) {
 #pragma unroll
       for (int q = 0; q < kLz - 1; ++q)
-        if (q < S) x = (row == iq[q]) ? ((c == kq[q]) ? (T)1 : (T)0) : fma_t<T>(-gq[q], vval(q, c), x);
+        if (q < S) x = (row == iq[q]) ? ((c == kq[q]) ? 1.0 : 0.0) : fma(-gq[q], vval(q, c), x);
       return x;
     };
-    const T g = replay(col_ld<T>(W + (int64_t)ks * m, ro), ks);
-    if (!wout && valid) col_st<T>(G + (int64_t)S * m, ro, g);
-    RowBest<T> rb;
+    const double g = replay(col_ld<double>(WB + (int64_t)ks * m, ro8), ks);
+    if (!wout && valid) col_st<double>(G + (int64_t)S * m, ro8, g);
+    RowBest<double> rb;
     {
       // all rounds unrolled (r <= RMAX): no loop header at which the compiler
       // would wait for every outstanding load
@@ -353,20 +366,20 @@ void k_pass(Node* nodes, unsigned long long* prof) {
       for (int q = 0; q < (RMAX + NR - 1) / NR; ++q) {
         const int c0 = q * NR;
         if (c0 >= r) break;
-        T bs[NR];
+        double bs[NR];
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
           const int cc = min(c0 + u, r - 1);  // in range; extra lanes of the round are ignored
-          bs[u] = col_ld<T>(W + (int64_t)cc * m, ro);
+          bs[u] = col_ld<double>(WB + (int64_t)cc * m, ro8);
         }
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
           const int c = c0 + u;
           if (c < r) {
-            T b = fma_t<T>(-g, vval(S, c), replay(bs[u], c));
-            if (row == is) b = (c == ks) ? (T)1 : (T)0;
+            double b = fma(-g, vval(S, c), replay(bs[u], c));
+            if (row == is) b = (c == ks) ? 1.0 : 0.0;
             if (valid) {
-              if (wout) col_st<T>(W + (int64_t)c * m, ro, b);
+              if (wout) col_st<double>(WB + (int64_t)c * m, ro8, b);
               rb.take(b, c);
             }
           }
@@ -376,10 +389,16 @@ void k_pass(Node* nodes, unsigned long long* prof) {
     rb.to_cand(best, row, r);
   }
 
-  int64_t cols;  // algorithmic columns: working and history columns read + columns written
-  if (st == ST_ACA) cols = (nd.t == 0) ? nd.na : 2 * nd.na - 1;
-  else cols = (int64_t)r + nd.lz + ((nd.lz == kLz - 1) ? r : 1);
-  pass_finish(nd, tile, best, sc, prof, m * cols * (int64_t)sizeof(T));
+  // algorithmic bytes: every working and history column read, every column
+  // written (the panel in the input type, everything else FP64)
+  int64_t bytes;
+  if (st == ST_ACA) {
+    const int64_t na = nd.na, es = (nd.t <= 1) ? (int64_t)sizeof(T) : 8;
+    bytes = (nd.t == 0) ? na * es : na * es + (na - 1) * 8;
+  } else {
+    bytes = ((int64_t)r + nd.lz + ((nd.lz == kLz - 1) ? r : 1)) * 8;
+  }
+  pass_finish(nd, tile, best, sc, prof, m * bytes);
 }
 
 // Fresh B = A(:, J) X over one tile of kTileRows rows (X = A(I, J)^-1, r x r
@@ -403,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   const int64_t row0 = (int64_t)tile * kTileRows;
   const int64_t row = row0 + tid;
   const bool valid = row < m;
-  T* W = (T*)nd.work;
+  double* W = (double*)nd.work;
   const T* P = (const T*)nd.panel;
 
   constexpr int CB = RMAX <= 64 ? RMAX : 16;  // columns of X staged per chunk
@@ -421,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   }
   __syncthreads();
   const int slot = sslot[tid];
-  RowBest<T> rb;
+  RowBest<double> rb;
   for (int c0 = 0; c0 < r; c0 += CB) {
     const int nb = min(CB, r - c0);
     __syncthreads();
@@ -450,8 +469,8 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
       for (int j = 0; j < CB; ++j) {
         if (j < nb) {
           const int c = c0 + j;
-          T b = (T)acc[j];
-          if (slot >= 0) b = (c == slot) ? (T)1 : (T)0;
+          double b = acc[j];
+          if (slot >= 0) b = (c == slot) ? 1.0 : 0.0;
           W[(int64_t)c * m + row] = b;
           if (slot < 0) rb.take(b, c);
         }
@@ -460,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   }
   Cand best = cand_none();
   rb.to_cand(best, row, r);
-  pass_finish(nd, tile, best, sc, prof, m * 2 * (int64_t)r * (int64_t)sizeof(T));
+  pass_finish(nd, tile, best, sc, prof, m * (int64_t)r * ((int64_t)sizeof(T) + 8));
 }
 
 template <typename T, int RMAX>

@@ -219,10 +219,20 @@ __global__ __launch_bounds__(kThreads) void k_resid_final(const double* part, in
   }
 }
 
+// Scratch of one residual call: [Bm FP64 m x r | tile partials | final sums |
+// reduced-precision operands].
+static size_t residual_need(int64_t m, int64_t n, int r, int prec) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const bool mp = prec != CUR_PREC_NATIVE;
+  const int64_t nb = mp ? residual_mp_tiles(m, n) : ((n + kRT - 1) / kRT) * ((m + kRT - 1) / kRT);
+  return al(sizeof(double) * m * r) + al(sizeof(double) * 3 * nb) + 256 + (mp ? residual_mp_scratch(m, n, r, prec) : 0);
+}
+
+// The residual with its temporaries at `base` (residual_need bytes).
 template <typename T>
-static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
+static cur_status residual_core(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
                                 const T* C, const double* U, const T* R, int prec, double* cheb,
-                                double* fro_rel) {
+                                double* fro_rel, char* base) {
   hipStream_t s = ctx->stream;
   const bool mp = prec != CUR_PREC_NATIVE;  // FP32 input only (checked by the API)
   const int64_t gx = (n + kRT - 1) / kRT, gy = (m + kRT - 1) / kRT;
@@ -230,9 +240,6 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t sbm = al(sizeof(double) * m * r), spart = al(sizeof(double) * 3 * nb);
   const size_t smp = mp ? residual_mp_scratch(m, n, r, prec) : 0;
-  cur_status st = ensure_arena(ctx, sbm + spart + 256 + smp);
-  if (st != CUR_OK) return st;
-  char* base = (char*)ctx->arena;
   double* Bm = (double*)base;
   double* part = (double*)(base + sbm);
   double* out = (double*)(base + sbm + spart);
@@ -245,7 +252,8 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   int64_t nparts = nb;
   if (mp) {
     if constexpr (std::is_same<T, float>::value) {
-      st = residual_mp_launch(ctx, A, m, n, lda, r, Bm, R, prec, base + sbm + spart + 256, smp, part, &nparts);
+      cur_status st = residual_mp_launch(ctx, A, m, n, lda, r, Bm, R, prec, base + sbm + spart + 256, smp, part,
+                                         &nparts);
       if (st != CUR_OK) return st;
     } else {
       set_error("reduced-precision residual needs FP32 input");
@@ -271,6 +279,15 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
     return CUR_ERR_NONFINITE;
   }
   return CUR_OK;
+}
+
+template <typename T>
+static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
+                                const T* C, const double* U, const T* R, int prec, double* cheb,
+                                double* fro_rel) {
+  cur_status st = ensure_arena(ctx, residual_need(m, n, r, prec));
+  if (st != CUR_OK) return st;
+  return residual_core<T>(ctx, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel, (char*)ctx->arena);
 }
 
 cur_status residual_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,

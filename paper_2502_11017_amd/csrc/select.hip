@@ -879,12 +879,18 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     }
     __syncthreads();
     if (L.s.mode == M_EXIT) {
-      // f_c = R(i*, c) / p in the working precision, read from the residual the
-      // pass just wrote (the panel itself after the first, read-only, pass)
-      const T* R = (L.s.t == 1) ? (const T*)nd.panel : (const T*)nd.work;
+      // f_c = R(i*, c) / p in FP64, read from the residual the pass just wrote
+      // (FP64 for either input type; the panel itself after the first,
+      // read-only, pass)
       const int64_t wr = L.s.pend_i;
-      const T p = (T)L.s.pend_p;
-      for (int c = tid; c < L.s.na; c += kThreads) nd.vec[c] = (double)(R[(int64_t)c * m + wr] / p);
+      const double p = L.s.pend_p;
+      if (L.s.t == 1) {
+        const T* R = (const T*)nd.panel;
+        for (int c = tid; c < L.s.na; c += kThreads) nd.vec[c] = (double)R[(int64_t)c * m + wr] / p;
+      } else {
+        const double* R = (const double*)nd.work;
+        for (int c = tid; c < L.s.na; c += kThreads) nd.vec[c] = R[(int64_t)c * m + wr] / p;
+      }
     }
   } else if (st0 == ST_ROW_FRESH || st0 == ST_ROW_SWAP) {
     ctl_reduce(nd, L);
@@ -915,18 +921,17 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     if (L.s.mode == M_SWAPVEC) {
       // v_c = B(i*, c) / p with row i* of the current B: the working matrix
       // plus the pending swaps, replayed in the pass's own operation order
-      const T* B = (const T*)nd.work;
-      const T* G = (const T*)nd.lzg;
+      const double* B = (const double*)nd.work;
+      const double* G = (const double*)nd.lzg;
       const int64_t wr = L.s.pend_i;
-      const T p = (T)L.s.pend_p;
+      const double p = L.s.pend_p;
       const int ks = L.s.pend_k;
       const int S = L.s.lz;
       for (int c = tid; c < r; c += kThreads) {
-        T x = B[(int64_t)c * m + wr];
+        double x = B[(int64_t)c * m + wr];
         for (int q = 0; q < S; ++q)
-          x = (wr == nd.lzi[q]) ? ((c == nd.lzk[q]) ? (T)1 : (T)0)
-                                : fma_t<T>(-G[(int64_t)q * m + wr], (T)nd.lzv[q * r + c], x);
-        nd.lzv[S * r + c] = (c == ks) ? (double)((p - (T)1) / p) : (double)(x / p);
+          x = (wr == nd.lzi[q]) ? ((c == nd.lzk[q]) ? 1.0 : 0.0) : fma(-G[(int64_t)q * m + wr], nd.lzv[q * r + c], x);
+        nd.lzv[S * r + c] = (c == ks) ? (p - 1.0) / p : x / p;
       }
       if (tid == 0) {
         nd.lzi[S] = wr;
@@ -1440,9 +1445,9 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         set_error("A is zero");
         continue;
       }
-      // FP64: max(m,n) 2^-52 ||A||_C, the oracle's threshold.  FP32 path: the
-      // rounding accumulated by r elimination steps in FP32, r 2^-23 ||A||_C.
-      jb.theta = sizeof(T) == 8 ? (double)std::max(jb.m, jb.n) * 0x1p-52 * amax : (double)jb.r * 0x1p-23 * amax;
+      // max(m,n) 2^-52 ||A||_C for both input types: the ACA pivots are FP64
+      // (FP32 input widened exactly), so the rank decisions are the oracle's.
+      jb.theta = (double)std::max(jb.m, jb.n) * 0x1p-52 * amax;
     }
   }
 
@@ -1492,7 +1497,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     const int64_t m = jb.m;
     size_t per = 0;
     per += al(sizeof(T) * m * nc);                // panel
-    per += al(sizeof(T) * m * wd);                // work
+    per += al(sizeof(double) * m * wd);           // work: ACA residual, then B (FP64)
     per += al(sizeof(double) * r * r);            // X
     per += al(sizeof(double) * r * nc);           // Bc
     per += al(sizeof(double) * (wd + 128 + nc));  // vec (w | rowk)
@@ -1502,7 +1507,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     per += al(nc);                                // insel
     per += al(sizeof(int64_t) * r) + al(sizeof(int32_t) * r);
     per += al(sizeof(double) * 4 * kDbgRing);
-    per += al(sizeof(T) * m * kLz);               // swap history: columns g_s
+    per += al(sizeof(double) * m * kLz);          // swap history: columns g_s
     per += al(sizeof(double) * kLz * r);          // swap history: factors v_s
     return per;
   };
@@ -1550,7 +1555,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         nd.tau = jb.o.tau;
         nd.theta = jb.theta;
         nd.panel = ar.take(sizeof(T) * jb.m * nc);
-        nd.work = ar.take(sizeof(T) * jb.m * wd);
+        nd.work = ar.take(sizeof(double) * jb.m * wd);
         nd.X = (double*)ar.take(sizeof(double) * r * r);
         nd.Bc = (double*)ar.take(sizeof(double) * r * nc);
         nd.vec = (double*)ar.take(sizeof(double) * (wd + 128 + nc));
@@ -1562,7 +1567,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
         nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
         nd.dbg = (double*)ar.take(sizeof(double) * 4 * kDbgRing);
-        nd.lzg = ar.take(sizeof(T) * jb.m * kLz);
+        nd.lzg = ar.take(sizeof(double) * jb.m * kLz);
         nd.lzv = (double*)ar.take(sizeof(double) * kLz * r);
         if (!nd.panel || !nd.work || !nd.insel || !nd.Jp || !nd.dbg || !nd.lzv) {
           set_error("workspace layout overflow");
