@@ -174,6 +174,35 @@ cur_status cur_residual(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, in
                         int32_t r, const void* C, const double* U, const void* R, int32_t prec,
                         double* cheb, double* fro_rel);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): cur_residual
+ * with the same arguments, results and kernels, but every temporary (the
+ * m x r product C U in FP64, the split operands of the BF16X3 / FP8 forms, the
+ * per-tile partial sums) placed in a fixed device array of
+ * CUR_NOALLOC_SCRATCH_BYTES that the library holds on each GPU, instead of the
+ * context's growable workspace.  The call allocates nothing (no hipMalloc, no
+ * hipFree); the array is set up by cur_create on each device (with that device
+ * current) and lives until the process ends.
+ *   Limit: the call needs
+ *     align(8 m r) + align(24 ceil(m/128) ceil(n/128)) + 256 bytes (NATIVE),
+ *   plus, for BF16X3 / FP8, align(s m r32) x 2 + align(s n r32) x 2 +
+ *   align(4 m) + align(4 n) + 256 with r32 = r rounded up to 32, s = 2 / 1
+ *   bytes, align() rounding up to 256 bytes (for FP8 the tile count uses
+ *   128 x 128 tiles as well); more than CUR_NOALLOC_SCRATCH_BYTES returns
+ *   CUR_ERR_ARG before any device work (e.g. FP64 with m = 8192, n = 8192,
+ *   r = 64 needs 4.1 MiB; m r up to about 2 million fits NATIVE).
+ *   Sharing: every call on one GPU, from any context or thread, uses that
+ *   GPU's one array, which keeps the last call's contents.  Calls that overlap
+ *   in time on one GPU (two streams, two host threads) race on it and may
+ *   return wrong results: serialize them.  Nothing in it needs to start at
+ *   zero.
+ */
+#define CUR_NOALLOC_SCRATCH_BYTES (16u << 20)
+cur_status cur_residual_noalloc(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                int32_t r, const void* C, const double* U, const void* R, int32_t prec,
+                                double* cheb, double* fro_rel);
+
 /* One independent selection of a batch. */
 typedef struct {
   int32_t dtype; /* cur_dtype                        */

@@ -30,7 +30,9 @@ TRACE_FIELDS = ("level", "index", "q", "short", "promoted", "nocap", "swaps", "p
 
 EXPORTS = ("cur_opts_init", "cur_create", "cur_destroy", "cur_strerror", "cur_last_error",
            "cur_select", "cur_assemble", "cur_residual", "cur_select_batched",
-           "cur_profile_enable", "cur_profile_read", "cur_tune_export", "cur_tune_import")
+           "cur_profile_enable", "cur_profile_read", "cur_tune_export", "cur_tune_import",
+           "cur_residual_noalloc")
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class CurError(RuntimeError):
@@ -105,6 +107,9 @@ def lib():
         L.cur_residual.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, i32,
                                    ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.cur_residual.restype = ctypes.c_int
+        L.cur_residual_noalloc.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, i32,
+                                           ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.cur_residual_noalloc.restype = ctypes.c_int
         L.cur_select_batched.argtypes = [P, i32, ctypes.POINTER(Item), ctypes.POINTER(Opts),
                                          ctypes.POINTER(ctypes.c_int)]
         L.cur_select_batched.restype = ctypes.c_int
@@ -260,6 +265,25 @@ def residual(A, C, U, R, prec: int = PREC_NATIVE):
     rc = lib().cur_residual(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
                             ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
                             ctypes.c_void_p(R.data_ptr()), int(prec), ctypes.byref(cheb), ctypes.byref(fro))
+    _check(rc)
+    return cheb.value, fro.value
+
+
+def residual_noalloc(A, C, U, R, prec: int = PREC_NATIVE):
+    """cur_residual_noalloc: the residual with every temporary in the library's
+    fixed per-GPU scratch array (no device allocation; calls on one GPU must
+    not overlap)."""
+    m, n, lda = _matrix(A)
+    r = int(U.shape[0])
+    ctx = context(A.device.index)
+    C = C.contiguous()
+    U = U.contiguous()
+    R = R.contiguous()
+    cheb = ctypes.c_double()
+    fro = ctypes.c_double()
+    rc = lib().cur_residual_noalloc(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
+                                    ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                                    ctypes.c_void_p(R.data_ptr()), int(prec), ctypes.byref(cheb), ctypes.byref(fro))
     _check(rc)
     return cheb.value, fro.value
 

@@ -170,6 +170,15 @@ cur_status cur_create(cur_ctx* out, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
   else c->cu_count = 256;
+  cur_status ns = noalloc_init(device);  // device address of this GPU's no-allocation scratch
+  if (ns != CUR_OK) {
+    hipHostFree(c->host_flag);
+    delete c->prof_ev;
+    delete c->prof_kind;
+    delete c->tune;
+    delete c;
+    return ns;
+  }
   *out = c;
   return CUR_OK;
 }
@@ -249,6 +258,26 @@ cur_status cur_residual(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m,
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
   return residual_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
+}
+
+cur_status cur_residual_noalloc(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda,
+                                int32_t r, const void* C, const double* U, const void* R, int32_t prec,
+                                double* cheb, double* fro_rel) {
+  cur_status st = check_matrix(dtype_in, A, m, n, lda, r);
+  if (st != CUR_OK) return st;
+  const cur_dtype dtype = (cur_dtype)dtype_in;
+  if (!C || !U || !R) return arg_error("C, U and R must be non-NULL device pointers");
+  if (!cheb) return arg_error("cheb must be a non-NULL host pointer");
+  if (prec < CUR_PREC_NATIVE || prec > CUR_PREC_FP8) return arg_error("prec out of range");
+  if (dtype == CUR_F64 && prec != CUR_PREC_NATIVE) return arg_error("FP64 input takes CUR_PREC_NATIVE");
+  const size_t need = residual_noalloc_need(m, n, r, prec);
+  if (need > CUR_NOALLOC_SCRATCH_BYTES)
+    return arg_error("the call needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                     std::to_string(CUR_NOALLOC_SCRATCH_BYTES) + " bytes of CUR_NOALLOC_SCRATCH_BYTES");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return residual_noalloc_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
 }
 
 cur_status cur_tune_export(cur_ctx ctx, cur_tune_entry* out, int32_t cap, int32_t* count) {

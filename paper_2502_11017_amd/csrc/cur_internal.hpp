@@ -193,6 +193,14 @@ cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t 
 cur_status assemble_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                              int64_t lda, int r, const int64_t* I, const int64_t* J, void* C,
                              double* U, void* R);
+// The residual entry point that allocates nothing (residual.hip): its
+// scratch is a fixed device array whose address on `device` noalloc_init looks
+// up (once per device, with that device current).
+cur_status noalloc_init(int device);
+size_t residual_noalloc_need(int64_t m, int64_t n, int r, int prec);
+cur_status residual_noalloc_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                     int r, const void* C, const double* U, const void* R, int prec, double* cheb,
+                                     double* fro_rel);
 cur_status residual_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                              int64_t lda, int r, const void* C, const double* U, const void* R,
                              int prec, double* cheb, double* fro_rel);

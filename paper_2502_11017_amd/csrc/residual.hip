@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -288,6 +289,56 @@ static cur_status residual_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   cur_status st = ensure_arena(ctx, residual_need(m, n, r, prec));
   if (st != CUR_OK) return st;
   return residual_core<T>(ctx, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel, (char*)ctx->arena);
+}
+
+// ---- the entry point that allocates nothing ----
+// Its temporaries live in this fixed device array (one copy per GPU, held from
+// module load until the process ends).  Host code never passes `scratch`
+// itself (in host code that name is a stand-in, not a device address): the
+// device address of each GPU's copy is looked up once per device, with that
+// device current, by noalloc_init (called by cur_create) and kept in
+// g_noalloc_ptr.
+static __device__ __align__(256) unsigned char scratch[CUR_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* g_noalloc_ptr[kMaxDevices];
+static std::mutex g_noalloc_mu;
+
+cur_status noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device index beyond the library's per-device table");
+    return CUR_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return CUR_OK;
+  void* p = nullptr;
+  CUR_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) {
+    set_error("hipGetSymbolAddress returned NULL for the no-allocation scratch");
+    return CUR_ERR_DEVICE;
+  }
+  g_noalloc_ptr[device] = p;
+  return CUR_OK;
+}
+
+size_t residual_noalloc_need(int64_t m, int64_t n, int r, int prec) { return residual_need(m, n, r, prec); }
+
+cur_status residual_noalloc_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                     int r, const void* C, const double* U, const void* R, int prec, double* cheb,
+                                     double* fro_rel) {
+  void* p;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    p = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_noalloc_ptr[ctx->device] : nullptr;
+  }
+  if (!p) {
+    set_error("no-allocation scratch not set up for this device (cur_create did not complete)");
+    return CUR_ERR_DEVICE;
+  }
+  if (dtype == CUR_F64)
+    return residual_core<double>(ctx, (const double*)A, m, n, lda, r, (const double*)C, U, (const double*)R, prec,
+                                 cheb, fro_rel, (char*)p);
+  return residual_core<float>(ctx, (const float*)A, m, n, lda, r, (const float*)C, U, (const float*)R, prec, cheb,
+                              fro_rel, (char*)p);
 }
 
 cur_status residual_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,

@@ -32,6 +32,10 @@ int main() {
   bad |= cur_assemble(nullptr, CUR_F64, &dummy, 10, 12, 12, 3, &dummy, &dummy, nullptr, (double*)&dummy, &dummy) != CUR_ERR_ARG;
   double cheb;
   bad |= cur_residual(nullptr, CUR_F64, &dummy, 10, 12, 12, 3, &dummy, (double*)&dummy, &dummy, CUR_PREC_FP8, &cheb, nullptr) != CUR_ERR_ARG;
+  bad |= cur_residual_noalloc(nullptr, CUR_F64, &dummy, 40000, 64, 64, 64, &dummy, (double*)&dummy, &dummy, 0, &cheb,
+                              nullptr) != CUR_ERR_ARG;  // beyond CUR_NOALLOC_SCRATCH_BYTES
+  bad |= cur_residual_noalloc(nullptr, 9, &dummy, 100, 64, 64, 8, &dummy, (double*)&dummy, &dummy, 0, &cheb,
+                              nullptr) != CUR_ERR_ARG;  // dtype out of range
   cur_item it[2]; std::memset(it, 0, sizeof(it));
   bad |= cur_select_batched(nullptr, 2, it, nullptr, nullptr) != CUR_ERR_ARG;
   bad |= cur_select_batched(nullptr, -1, nullptr, nullptr, nullptr) != CUR_ERR_ARG;

@@ -135,3 +135,17 @@ def test_greedy_method_trace_needs_arrays_and_rejects_batching():
     items = (cur.Item * 1)(cur.Item(cur.F64, 3, 1, 10, 12, 12, 1, 1))
     assert L.cur_select_batched(None, 1, items, ctypes.byref(o), None) == cur.ERR_ARG
     assert "maximal-volume" in cur.last_error()
+
+
+def test_noalloc_residual_limit_is_checked_on_host():
+    """cur_residual_noalloc refuses, before any device work, a call whose
+    temporaries exceed CUR_NOALLOC_SCRATCH_BYTES (here 8 m r alone is 20 MB)."""
+    L = cur.lib()
+    p = ctypes.c_void_p(1)
+    cheb = ctypes.c_double()
+    assert L.cur_residual_noalloc(None, cur.F64, p, 40000, 64, 64, 64, p, p, p, 0, ctypes.byref(cheb),
+                                  None) == cur.ERR_ARG
+    assert "CUR_NOALLOC_SCRATCH_BYTES" in cur.last_error()
+    assert L.cur_residual_noalloc(None, cur.F64, p, 4000, 64, 64, 16, p, p, p, 0, ctypes.byref(cheb),
+                                  None) == cur.ERR_ARG
+    assert "ctx" in cur.last_error()
