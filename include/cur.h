@@ -184,14 +184,16 @@ cur_status cur_residual(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, in
  * context's growable workspace.  The call allocates nothing (no hipMalloc, no
  * hipFree); the array is set up by cur_create on each device (with that device
  * current) and lives until the process ends.
- *   Limit: the call needs
- *     align(8 m r) + align(24 ceil(m/128) ceil(n/128)) + 256 bytes (NATIVE),
- *   plus, for BF16X3 / FP8, align(s m r32) x 2 + align(s n r32) x 2 +
- *   align(4 m) + align(4 n) + 256 with r32 = r rounded up to 32, s = 2 / 1
- *   bytes, align() rounding up to 256 bytes (for FP8 the tile count uses
- *   128 x 128 tiles as well); more than CUR_NOALLOC_SCRATCH_BYTES returns
- *   CUR_ERR_ARG before any device work (e.g. FP64 with m = 8192, n = 8192,
- *   r = 64 needs 4.1 MiB; m r up to about 2 million fits NATIVE).
+ *   Limit: the call needs, with align() rounding up to 256 bytes and
+ *   T = ceil(m/128) ceil(n/128) tiles,
+ *     align(8 m r) + align(24 T) + align(24576) + 256 bytes (NATIVE);
+ *     align(24 T) + align(24576) + 2 align(s m r32) + 2 align(s n r32)
+ *       + 2 align(s r32 r32) + align(4 ceil(m/16)) + align(4 ceil(n/16))
+ *       + align(4 r32/16) + 512 bytes (BF16X3: s = 2, FP8: s = 1),
+ *   r32 = r rounded up to a multiple of 32.  A call needing more than
+ *   CUR_NOALLOC_SCRATCH_BYTES returns CUR_ERR_ARG before any device work
+ *   (e.g. FP64 with m = n = 8192, r = 64 needs 4.1 MiB; NATIVE fits m r up to
+ *   about 2 million).
  *   Sharing: every call on one GPU, from any context or thread, uses that
  *   GPU's one array, which keeps the last call's contents.  Calls that overlap
  *   in time on one GPU (two streams, two host threads) race on it and may

@@ -175,11 +175,12 @@ void fresh_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned 
 void pass_launch(bool f64, int rb, Node* nodes, int count, int tiles, unsigned long long* prof, hipStream_t s);
 
 // Reduced-precision residual (residual_mp.hip): scratch bytes, tile count, and
-// the launches that turn Bm (FP64, formed by the caller) into tile partials.
+// the launches that form Bm = C U and P = Bm R on MFMA and reduce E into tile
+// partials.
 size_t residual_mp_scratch(int64_t m, int64_t n, int r, int prec);
 int64_t residual_mp_tiles(int64_t m, int64_t n);
-cur_status residual_mp_launch(cur_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, int r,
-                              const double* Bm, const float* R, int prec, char* scratch, size_t scratch_bytes,
+cur_status residual_mp_launch(cur_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, int r, const float* C,
+                              const double* U, const float* R, int prec, char* scratch, size_t scratch_bytes,
                               double* part, int64_t* nb);
 
 // Independent selections of several matrices, run together per dtype and

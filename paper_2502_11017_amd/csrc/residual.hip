@@ -192,10 +192,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C
     }
 }
 
-// Deterministic final reduction of the tile partials (fixed order).
-__global__ __launch_bounds__(kThreads) void k_resid_final(const double* part, int64_t nb, double* out) {
+// Deterministic reduction of tile partials {max, sum, sum} (fixed order):
+// block g reduces entries [g chunk, (g + 1) chunk) into out[3 g ..].  Run once
+// with many blocks over the tile partials and once with one block over theirs.
+constexpr int kRedBlocks = 1024;
+__global__ __launch_bounds__(kThreads) void k_resid_reduce(const double* part, int64_t nb, int64_t chunk,
+                                                           double* out) {
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(nb, b0 + chunk);
   double emax = 0.0, esq = 0.0, asq = 0.0;
-  for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += kThreads) {
     emax = nan_max(emax, part[3 * b]);
     esq += part[3 * b + 1];
     asq += part[3 * b + 2];
@@ -214,19 +219,20 @@ __global__ __launch_bounds__(kThreads) void k_resid_final(const double* part, in
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = s[0][0];
-    out[1] = s[1][0];
-    out[2] = s[2][0];
+    out[3 * blockIdx.x + 0] = s[0][0];
+    out[3 * blockIdx.x + 1] = s[1][0];
+    out[3 * blockIdx.x + 2] = s[2][0];
   }
 }
 
-// Scratch of one residual call: [Bm FP64 m x r | tile partials | final sums |
-// reduced-precision operands].
+// Scratch of one residual call: [Bm FP64 m x r (native form only) | tile
+// partials | final sums | reduced-precision operands].
 static size_t residual_need(int64_t m, int64_t n, int r, int prec) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   const bool mp = prec != CUR_PREC_NATIVE;
   const int64_t nb = mp ? residual_mp_tiles(m, n) : ((n + kRT - 1) / kRT) * ((m + kRT - 1) / kRT);
-  return al(sizeof(double) * m * r) + al(sizeof(double) * 3 * nb) + 256 + (mp ? residual_mp_scratch(m, n, r, prec) : 0);
+  return (mp ? 0 : al(sizeof(double) * m * r)) + al(sizeof(double) * 3 * nb) + al(sizeof(double) * 3 * kRedBlocks) +
+         256 + (mp ? residual_mp_scratch(m, n, r, prec) : 0);
 }
 
 // The residual with its temporaries at `base` (residual_need bytes).
@@ -239,22 +245,23 @@ static cur_status residual_core(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   const int64_t gx = (n + kRT - 1) / kRT, gy = (m + kRT - 1) / kRT;
   const int64_t nb = mp ? residual_mp_tiles(m, n) : gx * gy;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t sbm = al(sizeof(double) * m * r), spart = al(sizeof(double) * 3 * nb);
+  const size_t sbm = mp ? 0 : al(sizeof(double) * m * r), spart = al(sizeof(double) * 3 * nb);
   const size_t smp = mp ? residual_mp_scratch(m, n, r, prec) : 0;
+  const size_t smid = al(sizeof(double) * 3 * kRedBlocks);
   double* Bm = (double*)base;
   double* part = (double*)(base + sbm);
-  double* out = (double*)(base + sbm + spart);
+  double* mid = (double*)(base + sbm + spart);
+  double* out = (double*)(base + sbm + spart + smid);
   const int64_t gm = (m + kRT - 1) / kRT;
   if (gm > 0x7fffffff) {
     set_error("matrix too tall for the residual grid");
     return CUR_ERR_ARG;
   }
-  hipLaunchKernelGGL((k_cu_mfma<T>), dim3((unsigned)gm), dim3(kThreads), 0, s, C, U, m, r, Bm);
   int64_t nparts = nb;
   if (mp) {
     if constexpr (std::is_same<T, float>::value) {
-      cur_status st = residual_mp_launch(ctx, A, m, n, lda, r, Bm, R, prec, base + sbm + spart + 256, smp, part,
-                                         &nparts);
+      cur_status st = residual_mp_launch(ctx, A, m, n, lda, r, C, U, R, prec, base + sbm + spart + smid + 256, smp,
+                                         part, &nparts);
       if (st != CUR_OK) return st;
     } else {
       set_error("reduced-precision residual needs FP32 input");
@@ -265,10 +272,14 @@ static cur_status residual_core(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
       set_error("matrix too tall for the residual grid");
       return CUR_ERR_ARG;
     }
+    hipLaunchKernelGGL((k_cu_mfma<T>), dim3((unsigned)gm), dim3(kThreads), 0, s, C, U, m, r, Bm);
     hipLaunchKernelGGL((k_resid_mfma<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
                        lda, r, Bm, R, part);
   }
-  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kThreads), 0, s, part, nparts, out);
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (nparts + kThreads - 1) / kThreads));
+  const int64_t chunk = (nparts + g - 1) / g;
+  hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)g), dim3(kThreads), 0, s, part, nparts, chunk, mid);
+  hipLaunchKernelGGL(k_resid_reduce, dim3(1), dim3(kThreads), 0, s, mid, g, g, out);
   CUR_HIP_CHECK(hipGetLastError());
   double h[3];
   CUR_HIP_CHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
