@@ -164,6 +164,44 @@ def bench_f1(cur, torch, A, r, res_maxvol, reps=3):
     return out
 
 
+def bench_e4(cur, torch, A, r, res_plain, t_plain, reps=3):
+    """The learned candidate proposal on the same C2 matrix: the selection
+    time with the shipped weights (features, scores, restricted starts and
+    the verifying swap loops included), the feature pass alone, and the
+    volume of the cross it ends with against the plain selection's."""
+    import numpy as np
+
+    from paper_2502_11017_amd import learn
+
+    blob = learn.load_blob(device=A.device)
+    if t_plain is None:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            cur.select(A, r)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - a) / reps
+    cur.select(A, r, mlp=blob, seed=7)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        g = cur.select(A, r, mlp=blob, seed=7)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+    a = time.perf_counter()
+    for _ in range(reps):
+        cur.mlp_features(A, r, seed=7)
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - a) / reps
+    out = {"workload": "C2 (same matrix), learned proposal with the shipped weights, FP64",
+           "select_ms": 1e3 * dt, "plain_select_ms": 1e3 * t_plain, "features_ms": 1e3 * tf,
+           "speedup_vs_plain": t_plain / dt, "status": g["status"], "swaps": g["swaps"],
+           "swaps_plain": res_plain["swaps"], "volume_ratio_vs_plain": float(np.exp(g["logvol"] - res_plain["logvol"]))}
+    log(f"e4: learned {1e3 * dt:.1f} ms (plain {1e3 * t_plain:.1f} ms, features {1e3 * tf:.2f} ms), "
+        f"volume ratio to the plain cross {out['volume_ratio_vs_plain']:.3f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +217,7 @@ def main():
     ap.add_argument("--no-e1", action="store_true",
                     help="skip the reduced-precision residual figures on the tall FP32 workload")
     ap.add_argument("--no-e2", action="store_true", help="skip the batched uneven-workload figures")
+    ap.add_argument("--no-e4", action="store_true", help="skip the learned-proposal figures")
     ap.add_argument("--no-f1", action="store_true", help="skip the norm-greedy (paper-literal) selection figures")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of the launch autotuner cache: loaded before the run when it exists, "
@@ -230,7 +269,7 @@ def main():
         step(A)
     torch.cuda.synchronize()
 
-    cur.profile_enable(True)
+    cur.profile_enable(2)  # events around every pass and fresh launch, on its own stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -266,10 +305,32 @@ def main():
         t_res, (cheb, fro) = timed(lambda: cur.residual(A, C, U, R))
         res_tflops = 2.0 * m * n * r / t_res / 1e12
 
-    pass_gbs = prof["bytes"] / prof["seconds"] / 1e9 if prof["seconds"] > 0 else 0.0
-    launches = max(prof["launches"], 1)
-    bytes_per_launch = prof["bytes"] / launches
+    def roof(kind):
+        """Roofline record of one row kernel over the timed region: achieved =
+        the in-place algorithm's bytes (an elimination step reads and writes
+        the active columns, a row swap the m x r matrix B, a fresh B reads
+        A(:, J) and writes B) / the summed HIP-event time of its launches; the
+        bytes this implementation moves (lazy row swaps) beside it."""
+        pre = "fresh_" if kind == "fresh" else ""
+        sec, n_l = prof[pre + "seconds"], max(prof[pre + "launches"], 1)
+        b_model, b_impl = prof[pre + "bytes_inplace"], prof[pre + "bytes"]
+        ach = b_model / sec / 1e9 if sec > 0 else 0.0
+        return {"bound": "hbm",
+                "kernel": ("k_fresh (fresh interpolation matrix B = A(:,J) A(I,J)^-1)" if kind == "fresh"
+                           else "k_pass (streaming row pass: ACA updates, row swaps)"),
+                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_launch": b_model / n_l,
+                "implementation_bytes_per_launch": b_impl / n_l,
+                "achieved_implementation_bytes_gbs": b_impl / sec / 1e9 if sec > 0 else 0.0,
+                "launches_per_step": prof[pre + "launches"] / max(args.steps, 1),
+                "busy_launches_per_step": prof[pre + "busy"] / max(args.steps, 1),
+                "avg_launch_us": 1e6 * sec / n_l}
+
+    roof_pass, roof_fresh = roof("pass"), roof("fresh")
+    pass_gbs = roof_pass["achieved"]
     traffic = measured_traffic()
+    roof_pass["traffic"] = traffic
+    roof_fresh["traffic"] = None
 
     I = res["I"].cpu().numpy()
     J = res["J"].cpu().numpy()
@@ -317,6 +378,9 @@ def main():
     e2 = None
     if not args.no_e2:
         e2 = bench_e2(cur, W, torch, dev)
+    e4 = None
+    if not args.no_e4:
+        e4 = bench_e4(cur, torch, A, r, res, t_sel)
 
     out = {
         "metric": "CUR selections/sec + swap-loop HBM GB/s at volume ratio >=0.99 vs FP64 oracle",
@@ -337,14 +401,8 @@ def main():
         "swap_loop_gbs": pass_gbs,
         "volume_ratio": vol_ratio,
         "indices_equal_oracle": exact,
-        "roofline": {"bound": "hbm", "kernel": "k_pass (streaming row pass: ACA updates, row swaps)",
-                     "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": pass_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "launches_per_step": prof["launches"] / max(args.steps, 1),
-                     "busy_launches_per_step": prof["busy"] / max(args.steps, 1),
-                     "avg_launch_us": 1e6 * prof["seconds"] / launches},
+        "roofline": roof_pass,
+        "roofline_fresh": roof_fresh,
         "stages_ms": None if args.no_stages else {"select": 1e3 * t_sel, "assemble": 1e3 * t_asm,
                                                   "residual": 1e3 * t_res},
         "residual": {"cheb": cheb, "fro_rel": fro, "tflops": res_tflops,
@@ -355,6 +413,7 @@ def main():
         "e1_reduced_precision_residual": e1,
         "e2_batched_uneven": e2,
         "f1_paper_greedy": f1,
+        "e4_learned_proposal": e4,
         "cpu_baseline": cpu,
     }
     if args.tune_cache:

@@ -79,13 +79,14 @@ typedef struct {
   double tau;          /* a swap happens iff |B| > 1 + tau; 0 -> 1e-13                           */
   int32_t max_swaps;   /* swap budget per tree node; 0 -> 64 r                                   */
   int32_t prec;        /* cur_prec of the assembly/residual GEMMs (selection itself is exact)    */
-  int32_t propose;     /* 0: no candidate proposal                                               */
+  int32_t propose;     /* 0: no candidate proposal; 1: learned proposal for the leaves (mlp, seed;
+                          see "Learned candidate proposal" below; r <= 64, cur_select only)    */
   int32_t groups;      /* node groups per tree level, each iterating on a stream of its own:
                           0 -> autotuned per level shape (the first calls on a shape try 1, 2
                           and 3 groups once each, later calls use the fastest); 1..3 fixed.
                           The result does not depend on it.                                     */
-  const void* mlp;     /* reserved (must be NULL when propose == 0)                              */
-  uint64_t seed;       /* reserved                                                               */
+  const void* mlp;     /* propose == 1: device weight blob (CUR_MLP_BLOB_BYTES); else NULL       */
+  uint64_t seed;       /* propose == 1: seed of the Gaussian sketch of the leverage feature      */
   cur_trace* trace;    /* host pointer or NULL: per-node tree records                            */
   int32_t method;      /* 0: maximal-volume tree (Alg. 1 leaves, swap loops, binary merge);
                           1: norm-greedy rows and columns (Alg. 2 with Alg. 3): r times the
@@ -224,11 +225,73 @@ typedef struct {
 cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items, const cur_opts* opts,
                               cur_status* per_item);
 
+/*
+ * Learned candidate proposal (cur_opts.propose = 1).
+ * A small MLP scores every row of every leaf block from four features; the
+ * leaf's 4r best rows are the candidates of a restricted start (adaptive
+ * cross approximation, Alg. 1, on the 4r candidate rows x the block's
+ * columns, held on chip) that replaces the r elimination passes over all m
+ * rows.  The leaf then runs the ordinary swap loop from that start: its first
+ * row phase forms A(:,J) A(I,J)^-1 over all m rows (verification) and swaps
+ * in every row of |B| > 1 + tau (fallback to plain maxvol), so every node
+ * still ends dominant; the selection may reach another dominant cross than
+ * the plain method.  A leaf whose candidate elimination finds a pivot at or
+ * below the rank threshold, or whose 4r x |block| submatrix exceeds
+ * 16384 doubles, keeps the plain start.
+ * Features of row i in leaf k, FP32, four per (leaf, row), leaf-major
+ * (F[(k m + i) 4 + f]):
+ *   f0 = log2 ||A(i, block_k)||^2 - log2 max_i ||A(i, block_k)||^2
+ *   f1 = log2(l_i m / s), l_i the leverage of row i in the column space of the
+ *        Gaussian sketch A Omega (Omega n x s, s = 2r, entries from a
+ *        counter-based generator of `seed`), by CholeskyQR2
+ *   f2 = log2(lb_i m / w_k), lb_i = a_i^T (A_k^T A_k + lambda I)^-1 a_i the
+ *        ridge leverage of a_i = A(i, block_k) in A_k = A(:, block_k) (width
+ *        w_k), lambda = 2^-20 max_j ||A_k(:, j)||^2
+ *   f3 = share of the leaf's rows with a larger f2 (1024-bin histogram)
+ * Network: score = w3 . relu(W2 relu(W1 f + b1) + b2) + b3, W1 128 x 4,
+ * W2 128 x 128, w3 128, FP16; biases FP32; FP32 accumulation.  Blob layout
+ * (bytes): W1 at 0 (row-major [128][4] FP16), W2 at 1024 ([128][128] FP16),
+ * w3 at 33792 (FP16), b1 at 34048 (FP32 [128]), b2 at 34560, b3 at 35072.
+ * Parameter vector (FP32, CUR_MLP_PARAMS): W1, b1, W2, b2, w3, b3 in that
+ * order, each row-major.
+ */
+#define CUR_MLP_FEATURES 4
+#define CUR_MLP_HIDDEN 128
+#define CUR_MLP_PARAMS 17281
+#define CUR_MLP_BLOB_BYTES 35328
+/* Features of every (leaf, row) of A for blocks of width col_block (0 ->
+ * max(64, r)): F device float[b m 4] with b = max(1, n / col_block). */
+cur_status cur_mlp_features(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,
+                            int32_t col_block, uint64_t seed, float* F);
+/* Scores of count feature rows (F device float[count 4] -> score device float[count]). */
+cur_status cur_mlp_forward(cur_ctx ctx, const void* blob, const float* F, int64_t count, float* score);
+/* Gradient of the mean weighted logistic loss
+ *   (1/count) sum_i [ pos_weight y_i softplus(-s_i) + (1 - y_i) softplus(s_i) ]
+ * with respect to the parameter vector: grad device float[CUR_MLP_PARAMS];
+ * y device float[count] in [0, 1]; loss host (nullable).  Deterministic. */
+cur_status cur_mlp_grad(cur_ctx ctx, const void* blob, const float* F, const float* y, int64_t count,
+                        float pos_weight, float* grad, double* loss);
+/* One Adam step (bias-corrected, step >= 1) on the FP32 parameter vector
+ * params with moments m1, m2 (device float[CUR_MLP_PARAMS] each); writes the
+ * updated weights into blob (FP16 weights, FP32 biases).  With lr = 0 it only
+ * packs params into blob. */
+cur_status cur_mlp_adam(cur_ctx ctx, void* blob, float* params, float* m1, float* m2, const float* grad, int32_t step,
+                        float lr, float beta1, float beta2, float eps);
+
 /* Measurement counters of the selection's row kernels.  While enabled,
  * cur_select and cur_select_batched bracket every launch of the two row
  * kernels with HIP events on the stream it is issued on, and count on the
- * device the algorithmic bytes each launch must move (every element of the
- * working columns it reads plus every element it writes, once):
+ * device two byte figures per launch:
+ *   bytes          what this implementation must move: every element of the
+ *                  working and history columns it reads plus every element
+ *                  it writes, once (row swaps are applied lazily, so a swap
+ *                  pass reads r + S columns and writes one);
+ *   bytes_inplace  what the plain in-place algorithm moves for the same
+ *                  steps: an elimination step with t pivots reads and writes
+ *                  the nc - t active columns, a row swap reads and writes the
+ *                  m x r matrix B, a fresh B reads A(:, J) and writes B, all
+ *                  in the input's element size.
+ * for the two kernels:
  *   pass   the streaming sweep: ACA rank-1 updates and Sherman-Morrison row
  *          swaps over the m x (active columns) working matrix;
  *   fresh  fresh interpolation matrices B = A(:, J) A(I, J)^-1.
@@ -238,11 +301,13 @@ typedef struct {
   int64_t launches;        /* pass launches timed                                 */
   int64_t busy;            /* pass launches in which some node had work           */
   double seconds;          /* summed event time of the pass launches              */
-  double bytes;            /* summed algorithmic bytes of the pass launches       */
-  int64_t fresh_launches;  /* the same four figures for the fresh kernel          */
+  double bytes;            /* summed bytes of the pass launches (implementation)  */
+  int64_t fresh_launches;  /* the same figures for the fresh kernel               */
   int64_t fresh_busy;
   double fresh_seconds;
   double fresh_bytes;
+  double bytes_inplace;        /* summed in-place-algorithm bytes, pass launches  */
+  double fresh_bytes_inplace;  /* the same for the fresh launches                 */
 } cur_profile;
 
 /* The launch-shape autotuner cache of a context (cur_opts.groups == 0).  One

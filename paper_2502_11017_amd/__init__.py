@@ -31,8 +31,9 @@ TRACE_FIELDS = ("level", "index", "q", "short", "promoted", "nocap", "swaps", "p
 EXPORTS = ("cur_opts_init", "cur_create", "cur_destroy", "cur_strerror", "cur_last_error",
            "cur_select", "cur_assemble", "cur_residual", "cur_select_batched",
            "cur_profile_enable", "cur_profile_read", "cur_tune_export", "cur_tune_import",
-           "cur_residual_noalloc")
+           "cur_residual_noalloc", "cur_mlp_features", "cur_mlp_forward", "cur_mlp_grad", "cur_mlp_adam")
 NOALLOC_SCRATCH_BYTES = 16 << 20
+MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS, MLP_BLOB_BYTES = 4, 128, 17281, 35328
 
 
 class CurError(RuntimeError):
@@ -68,7 +69,8 @@ class TuneEntry(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("busy", ctypes.c_int64), ("seconds", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("fresh_launches", ctypes.c_int64), ("fresh_busy", ctypes.c_int64),
-                ("fresh_seconds", ctypes.c_double), ("fresh_bytes", ctypes.c_double)]
+                ("fresh_seconds", ctypes.c_double), ("fresh_bytes", ctypes.c_double),
+                ("bytes_inplace", ctypes.c_double), ("fresh_bytes_inplace", ctypes.c_double)]
 
 
 class Item(ctypes.Structure):
@@ -110,6 +112,15 @@ def lib():
         L.cur_residual_noalloc.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, i32,
                                            ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.cur_residual_noalloc.restype = ctypes.c_int
+        L.cur_mlp_features.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, i32, ctypes.c_uint64, P]
+        L.cur_mlp_features.restype = ctypes.c_int
+        L.cur_mlp_forward.argtypes = [P, P, P, i64, P]
+        L.cur_mlp_forward.restype = ctypes.c_int
+        L.cur_mlp_grad.argtypes = [P, P, P, P, i64, ctypes.c_float, P, ctypes.POINTER(dbl)]
+        L.cur_mlp_grad.restype = ctypes.c_int
+        L.cur_mlp_adam.argtypes = [P, P, P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float]
+        L.cur_mlp_adam.restype = ctypes.c_int
         L.cur_select_batched.argtypes = [P, i32, ctypes.POINTER(Item), ctypes.POINTER(Opts),
                                          ctypes.POINTER(ctypes.c_int)]
         L.cur_select_batched.restype = ctypes.c_int
@@ -176,11 +187,16 @@ def _matrix(A):
     return A.shape[0], A.shape[1], A.stride(0)
 
 
-def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None, groups=0, method=0) -> Opts:
+def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None, groups=0, method=0,
+              mlp=None, seed=0) -> Opts:
     o = Opts()
     lib().cur_opts_init(ctypes.byref(o))
     o.groups = int(groups)
     o.method = int(method)
+    if mlp is not None:  # a device tensor holding the weight blob: the learned proposal
+        o.propose = 1
+        o.mlp = ctypes.c_void_p(mlp.data_ptr())
+        o.seed = int(seed)
     o.col_block = int(col_block)
     o.tau = float(tau)
     o.max_swaps = int(max_swaps)
@@ -201,7 +217,7 @@ def tree_size(n: int, w: int) -> int:
 
 
 def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, trace: bool = False,
-           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0, method: int = METHOD_MAXVOL):
+           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0, method: int = METHOD_MAXVOL, mlp=None, seed: int = 0):
     """Select r rows I and r columns J of the device matrix A (cur_select)."""
     torch = _torch()
     m, n, lda = _matrix(A)
@@ -220,7 +236,7 @@ def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, 
                 "I": np.zeros((N, r), dtype=np.int64), "J": np.zeros((N, r), dtype=np.int64)}
         tr = Trace(N, 0, host["meta"].ctypes.data, host["vol_m"].ctypes.data,
                    host["I"].ctypes.data, host["J"].ctypes.data)
-    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups, method=method)
+    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups, method=method, mlp=mlp, seed=seed)
     rc = lib().cur_select(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
                           ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                           ctypes.byref(info))
@@ -288,6 +304,59 @@ def residual_noalloc(A, C, U, R, prec: int = PREC_NATIVE):
     return cheb.value, fro.value
 
 
+def mlp_features(A, r: int, col_block: int = 0, seed: int = 0):
+    """Proposal features of every (leaf, row): float32 (b m, 4) on A's device."""
+    torch = _torch()
+    m, n, lda = _matrix(A)
+    w = col_block if col_block else max(64, r)
+    b = max(1, n // w)
+    F = torch.empty((b * m, MLP_FEATURES), dtype=torch.float32, device=A.device)
+    _check(lib().cur_mlp_features(context(A.device.index), _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda,
+                                  int(r), int(col_block), int(seed), ctypes.c_void_p(F.data_ptr())))
+    return F
+
+
+def mlp_forward(blob, F):
+    """Scores of the feature rows F (float32 (count, 4)) under the weight blob."""
+    torch = _torch()
+    F = F.contiguous()
+    out = torch.empty(F.shape[0], dtype=torch.float32, device=F.device)
+    _check(lib().cur_mlp_forward(context(F.device.index), ctypes.c_void_p(blob.data_ptr()),
+                                 ctypes.c_void_p(F.data_ptr()), int(F.shape[0]), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def mlp_grad(blob, F, y, pos_weight: float = 1.0):
+    """(gradient float32[MLP_PARAMS], mean loss) of the weighted logistic loss."""
+    torch = _torch()
+    F = F.contiguous()
+    y = y.to(torch.float32).contiguous()
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=F.device)
+    loss = ctypes.c_double()
+    _check(lib().cur_mlp_grad(context(F.device.index), ctypes.c_void_p(blob.data_ptr()), ctypes.c_void_p(F.data_ptr()),
+                              ctypes.c_void_p(y.data_ptr()), int(F.shape[0]), float(pos_weight),
+                              ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss)))
+    return g, loss.value
+
+
+def mlp_adam(blob, params, m1, m2, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step on params (float32[MLP_PARAMS], in place) that also writes the blob."""
+    _check(lib().cur_mlp_adam(context(params.device.index), ctypes.c_void_p(blob.data_ptr()),
+                              ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(m1.data_ptr()),
+                              ctypes.c_void_p(m2.data_ptr()), ctypes.c_void_p(grad.data_ptr()), int(step), float(lr),
+                              float(beta1), float(beta2), float(eps)))
+
+
+def mlp_pack(params):
+    """A weight blob (uint8 device tensor) holding the FP32 parameter vector params."""
+    torch = _torch()
+    blob = torch.zeros(MLP_BLOB_BYTES, dtype=torch.uint8, device=params.device)
+    z = torch.zeros_like(params)
+    p = params.clone()
+    mlp_adam(blob, p, z.clone(), z.clone(), z, 1, 0.0)
+    return blob
+
+
 def profile_enable(enable=True, device=None):
     """Set the row-kernel timing / algorithmic-byte counters (cleared): False
     or 0 off, True or 1 the streaming pass kernel, 2 also the fresh kernel."""
@@ -298,8 +367,10 @@ def profile_read(device=None) -> dict:
     p = Profile()
     _check(lib().cur_profile_read(context(device), ctypes.byref(p)))
     return {"launches": p.launches, "busy": p.busy, "seconds": p.seconds, "bytes": p.bytes,
+            "bytes_inplace": p.bytes_inplace,
             "fresh_launches": p.fresh_launches, "fresh_busy": p.fresh_busy,
-            "fresh_seconds": p.fresh_seconds, "fresh_bytes": p.fresh_bytes}
+            "fresh_seconds": p.fresh_seconds, "fresh_bytes": p.fresh_bytes,
+            "fresh_bytes_inplace": p.fresh_bytes_inplace}
 
 
 def tune_export(device=None) -> list:

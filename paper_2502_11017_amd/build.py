@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcur.so")
-SOURCES = ["api.hip", "select.hip", "pass.hip", "assemble.hip", "residual.hip", "residual_mp.hip", "greedy.hip"]
+SOURCES = ["api.hip", "select.hip", "pass.hip", "assemble.hip", "residual.hip", "residual_mp.hip", "greedy.hip",
+           "propose.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Every decision of the selection is taken on explicitly written fma() chains;

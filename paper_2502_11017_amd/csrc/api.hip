@@ -84,10 +84,16 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.max_swaps < 0) return arg_error("max_swaps must be >= 0");
   if (o.max_swaps == 0) o.max_swaps = 64 * r;
   if (o.prec < CUR_PREC_NATIVE || o.prec > CUR_PREC_FP8) return arg_error("prec out of range");
-  if (o.propose != 0) return arg_error("propose must be 0 (no learned proposal is implemented)");
+  if (o.propose != 0 && o.propose != 1) return arg_error("propose must be 0 (none) or 1 (learned proposal)");
+  if (o.propose == 1) {
+    if (!o.mlp) return arg_error("propose == 1 needs the weight blob in mlp");
+    if (r > 64) return arg_error("propose == 1 supports r <= 64");
+    if (o.col_block > 64) return arg_error("propose == 1 supports col_block <= 64");
+    if (o.method != 0) return arg_error("propose == 1 applies to the maximal-volume method only");
+  }
   if (o.groups < 0 || o.groups > 3) return arg_error("groups must be 0 (autotuned) or 1..3");
   if (o.method != 0 && o.method != 1) return arg_error("method must be 0 (maximal volume) or 1 (norm-greedy)");
-  if (o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
+  if (o.propose == 0 && o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
   if (o.trace) {
     int64_t b = n / o.col_block;
     if (b < 1) b = 1;
@@ -280,6 +286,55 @@ cur_status cur_residual_noalloc(cur_ctx ctx, int32_t dtype_in, const void* A, in
   return residual_noalloc_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
 }
 
+cur_status cur_mlp_features(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,
+                            int32_t col_block, uint64_t seed, float* F) {
+  cur_status st = check_matrix(dtype_in, A, m, n, lda, r);
+  if (st != CUR_OK) return st;
+  if (r > 64) return arg_error("the proposal features support r <= 64");
+  if (col_block < 0) return arg_error("col_block must be >= 0");
+  const int w = col_block == 0 ? (r > 64 ? r : 64) : col_block;
+  if (w < r) return arg_error("col_block must be >= r");
+  if (w > 64) return arg_error("the proposal features support col_block <= 64");
+  if (!F) return arg_error("F must be a non-NULL device pointer");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return propose_features(ctx, (cur_dtype)dtype_in, A, m, n, lda, r, w, seed, F);
+}
+
+cur_status cur_mlp_forward(cur_ctx ctx, const void* blob, const float* F, int64_t count, float* score) {
+  if (!blob || !F || !score) return arg_error("blob, F and score must be non-NULL device pointers");
+  if (count < 0) return arg_error("count must be >= 0");
+  if (!ctx) return arg_error("ctx is NULL");
+  if (count == 0) return CUR_OK;
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return mlp_forward_dispatch(ctx, blob, F, count, score);
+}
+
+cur_status cur_mlp_grad(cur_ctx ctx, const void* blob, const float* F, const float* y, int64_t count, float pos_weight,
+                        float* grad, double* loss) {
+  if (!blob || !F || !y || !grad) return arg_error("blob, F, y and grad must be non-NULL device pointers");
+  if (count < 1) return arg_error("count must be >= 1");
+  if (!(pos_weight > 0.0f)) return arg_error("pos_weight must be > 0");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return mlp_grad_dispatch(ctx, blob, F, y, count, pos_weight, grad, loss);
+}
+
+cur_status cur_mlp_adam(cur_ctx ctx, void* blob, float* params, float* m1, float* m2, const float* grad, int32_t step,
+                        float lr, float beta1, float beta2, float eps) {
+  if (!blob || !params || !m1 || !m2 || !grad) return arg_error("blob, params, m1, m2 and grad must be non-NULL");
+  if (step < 1) return arg_error("step must be >= 1");
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return arg_error("Adam hyper-parameters out of range");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return mlp_adam_dispatch(ctx, blob, params, m1, m2, grad, step, lr, beta1, beta2, eps);
+}
+
 cur_status cur_tune_export(cur_ctx ctx, cur_tune_entry* out, int32_t cap, int32_t* count) {
   if (!ctx || !count) return arg_error("ctx and count must be non-NULL");
   if (cap < 0 || (cap > 0 && !out)) return arg_error("out must hold cap >= 0 entries");
@@ -319,7 +374,7 @@ cur_status cur_profile_enable(cur_ctx ctx, int enable) {
   if (enable < 0 || enable > 2) return arg_error("enable must be 0, 1 or 2");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   if (enable && !ctx->prof_bytes)
-    CUR_HIP_CHECK(hipMalloc((void**)&ctx->prof_bytes, sizeof(unsigned long long) * cur::kProfSlots));
+    CUR_HIP_CHECK(hipMalloc((void**)&ctx->prof_bytes, sizeof(unsigned long long) * 2 * cur::kProfSlots));
   std::memset(&ctx->prof, 0, sizeof(ctx->prof));
   ctx->prof_on = enable;
   return CUR_OK;
@@ -338,6 +393,8 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
   if (opts && opts->trace) return arg_error("opts->trace must be NULL for batched selection");
   if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->method != 0)
     return arg_error("batched selection supports the maximal-volume method only");
+  if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->propose != 0)
+    return arg_error("batched selection supports no candidate proposal");
   for (int32_t i = 0; i < count; ++i) {
     const cur_item& it = items[i];
     cur_status st = check_matrix(it.dtype, it.A, it.m, it.n, it.lda, it.r);

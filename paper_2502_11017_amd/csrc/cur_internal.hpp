@@ -194,6 +194,19 @@ cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t 
 cur_status assemble_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                              int64_t lda, int r, const int64_t* I, const int64_t* J, void* C,
                              double* U, void* R);
+// Learned candidate proposal (propose.hip).
+size_t propose_scratch(int64_t m, int64_t n, int r, int b);
+template <typename T>
+cur_status propose_leaves(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r, int w, int b,
+                          const void* mlp, uint64_t seed, Node* leaves, char* scratch);
+cur_status propose_features(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda, int r, int w,
+                            uint64_t seed, float* F);
+cur_status mlp_forward_dispatch(cur_ctx ctx, const void* blob, const float* F, int64_t count, float* score);
+cur_status mlp_grad_dispatch(cur_ctx ctx, const void* blob, const float* F, const float* Y, int64_t count, float pw,
+                             float* grad, double* loss);
+cur_status mlp_adam_dispatch(cur_ctx ctx, void* blob, float* p, float* m1, float* m2, const float* g, int t, float lr,
+                             float beta1, float beta2, float eps);
+
 // The residual entry point that allocates nothing (residual.hip): its
 // scratch is a fixed device array whose address on `device` noalloc_init looks
 // up (once per device, with that device current).

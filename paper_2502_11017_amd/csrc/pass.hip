@@ -139,13 +139,19 @@ __device__ __forceinline__ float lane_read(float v, int l) {
 __device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 // Tile epilogue of both row kernels: block argmax, the tile winner to the
-// node's partial array, and (when profiling) the node's algorithmic bytes,
-// added once per node by its first tile.
+// node's partial array, and (when profiling) the node's bytes, added once per
+// node by its first tile to the launch's two slots: prof[0] the bytes this
+// implementation must move, prof[1] those of the plain in-place algorithm
+// (an elimination step or a row swap reads and writes the whole active
+// working matrix; a fresh B reads A(:, J) and writes B).
 __device__ __forceinline__ void pass_finish(Node& nd, int tile, Cand best, Cand* sc, unsigned long long* prof,
-                                            int64_t node_bytes) {
+                                            int64_t node_bytes, int64_t model_bytes) {
   best = block_argmax(best, sc);
   if (threadIdx.x == 0) {
-    if (prof && tile == 0) atomicAdd(prof, (unsigned long long)node_bytes);
+    if (prof && tile == 0) {
+      atomicAdd(prof, (unsigned long long)node_bytes);
+      atomicAdd(prof + 1, (unsigned long long)model_bytes);
+    }
     Partial p;
     p.val = best.val;
     p.sval = best.sval;
@@ -391,14 +397,19 @@ void k_pass(Node* nodes, unsigned long long* prof) {
 
   // algorithmic bytes: every working and history column read, every column
   // written (the panel in the input type, everything else FP64)
-  int64_t bytes;
+  // The in-place model counts an elimination step at t pivots as a read and a
+  // write of the nc - t active columns, a row swap as a read and a write of
+  // the m x r matrix B, in the input's element size.
+  int64_t bytes, model;
   if (st == ST_ACA) {
     const int64_t na = nd.na, es = (nd.t <= 1) ? (int64_t)sizeof(T) : 8;
     bytes = (nd.t == 0) ? na * es : na * es + (na - 1) * 8;
+    model = 2 * (int64_t)(nd.nc - nd.t) * (int64_t)sizeof(T);
   } else {
     bytes = ((int64_t)r + nd.lz + ((nd.lz == kLz - 1) ? r : 1)) * 8;
+    model = 2 * (int64_t)r * (int64_t)sizeof(T);
   }
-  pass_finish(nd, tile, best, sc, prof, m * bytes);
+  pass_finish(nd, tile, best, sc, prof, m * bytes, m * model);
 }
 
 // Fresh B = A(:, J) X over one tile of kTileRows rows (X = A(I, J)^-1, r x r
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   }
   Cand best = cand_none();
   rb.to_cand(best, row, r);
-  pass_finish(nd, tile, best, sc, prof, m * (int64_t)r * ((int64_t)sizeof(T) + 8));
+  pass_finish(nd, tile, best, sc, prof, m * (int64_t)r * ((int64_t)sizeof(T) + 8), 2 * m * (int64_t)r * (int64_t)sizeof(T));
 }
 
 template <typename T, int RMAX>

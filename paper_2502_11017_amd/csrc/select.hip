@@ -1145,7 +1145,7 @@ static void row_launch(cur_ctx ctx, int kind, int rb, Node* nodes, int count, in
     return;
   }
   (void)hipEventRecord(e0, s);
-  go(ctx->prof_bytes + pair);
+  go(ctx->prof_bytes + 2 * pair);
   (void)hipEventRecord(e1, s);
   if (ctx->prof_kind->size() <= pair) ctx->prof_kind->resize(pair + 1);
   (*ctx->prof_kind)[pair] = kind;
@@ -1512,6 +1512,8 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     return per;
   };
   size_t bytes = 4096;  // done counters (16 per level)
+  const bool propose = nj == 1 && jobs[0].active && jobs[0].o.propose == 1;
+  if (propose) bytes += propose_scratch(jobs[0].m, jobs[0].n, jobs[0].r, jobs[0].b) + 256;
   bytes += al(sizeof(Node) * total);
   bytes += al(sizeof(RootOut) * nj);
   for (const TreeJob<T>& jb : jobs)
@@ -1612,7 +1614,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   CUR_HIP_CHECK(hipMemcpyAsync(d_nodes, h.data(), sizeof(Node) * total, hipMemcpyHostToDevice, s));
   CUR_HIP_CHECK(hipMemcpyAsync(d_roots, roots.data(), sizeof(RootOut) * roots.size(), hipMemcpyHostToDevice, s));
   CUR_HIP_CHECK(hipMemsetAsync(d_done, 0, 4096, s));
-  if (ctx->prof_on) CUR_HIP_CHECK(hipMemsetAsync(ctx->prof_bytes, 0, sizeof(unsigned long long) * kProfSlots, s));
+  if (ctx->prof_on) CUR_HIP_CHECK(hipMemsetAsync(ctx->prof_bytes, 0, sizeof(unsigned long long) * 2 * kProfSlots, s));
 
   int fixed_groups = 0;
   for (const TreeJob<T>& jb : jobs)
@@ -1629,6 +1631,17 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     hipLaunchKernelGGL(k_leaf_init, dim3(b), dim3(kThreads), 0, s, d_nodes);
     hipLaunchKernelGGL((k_panel_from_A<T>), dim3((maxm + kTR - 1) / kTR, (leafmax + 63) / 64, b), dim3(kThreads),
                        0, s, d_nodes);
+    if (propose) {  // learned candidates: the restricted start of every leaf that admits one
+      const TreeJob<T>& jb = jobs[0];
+      char* scratch = (char*)ar.take(propose_scratch(jb.m, jb.n, jb.r, jb.b));
+      if (!scratch) {
+        set_error("workspace layout overflow");
+        return CUR_ERR_INTERNAL;
+      }
+      cur_status prc = propose_leaves<T>(ctx, jb.A, jb.m, jb.n, jb.lda, jb.r, jb.w, jb.b, jb.o.mlp, jb.o.seed, d_nodes,
+                                         scratch);
+      if (prc != CUR_OK) return prc;
+    }
     const int64_t key[6] = {f64, rb, b, maxtiles, maxm, 1};
     int cand = -1;
     const int groups = tune_pick(ctx, key, fixed_groups, &cand);
@@ -1676,23 +1689,26 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   CUR_HIP_CHECK(hipStreamSynchronize(s));
   if (ctx->prof_on && prof_used >= 2) {
     const size_t pairs = prof_used / 2;
-    std::vector<unsigned long long> hb(pairs);
-    CUR_HIP_CHECK(hipMemcpy(hb.data(), ctx->prof_bytes, sizeof(unsigned long long) * pairs, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> hb(2 * pairs);
+    CUR_HIP_CHECK(hipMemcpy(hb.data(), ctx->prof_bytes, sizeof(unsigned long long) * 2 * pairs, hipMemcpyDeviceToHost));
     std::vector<hipEvent_t>& ev = *ctx->prof_ev;
     for (size_t k = 0; k < pairs; ++k) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) continue;
       cur_profile& p = ctx->prof;
+      const unsigned long long b = hb[2 * k], bm = hb[2 * k + 1];
       if ((*ctx->prof_kind)[k] == 1) {
         p.fresh_launches += 1;
-        p.fresh_busy += hb[k] > 0;
+        p.fresh_busy += b > 0;
         p.fresh_seconds += 1e-3 * ms;
-        p.fresh_bytes += (double)hb[k];
+        p.fresh_bytes += (double)b;
+        p.fresh_bytes_inplace += (double)bm;
       } else {
         p.launches += 1;
-        p.busy += hb[k] > 0;
+        p.busy += b > 0;
         p.seconds += 1e-3 * ms;
-        p.bytes += (double)hb[k];
+        p.bytes += (double)b;
+        p.bytes_inplace += (double)bm;
       }
     }
   }

@@ -24,6 +24,13 @@ Named configurations (all sizes as stated):
     {8, 16, 32, 64}, s_i = q^i with q uniform in [0.8, 0.95].
   * ``c4``: 1,048,576 x 1024 FP32, G1 (m x 128) G2 (128 x n) with entries of
     variance 1/128 plus noise of standard deviation 1e-4.
+  * ``c5_train(seed)``: the training matrices of the learned proposal, the c2
+    construction at 4096 x 4096 with the flat 1e-6 floor of the spectrum
+    replaced by i.i.d. Gaussian entries of the same size (standard deviation
+    1e-6 / sqrt(n), whose singular values spread over [0, 2e-6]) merged with
+    the noise of standard deviation 1e-7: only the 64 leading directions need
+    Q factors (two reduced QRs of n x 64 instead of two full n x n ones), so
+    the matrices can be generated as they are consumed.
   * ``hilbert(n)``: H(i,j) = 1/(i+j-1), 1-based (Sec. 3.1).
   * ``recip_lowrank(n, r)``: H = A B with A(i,j) = B(i,j) = 1/(i+j), 1-based,
     A n x r, B r x n (Sec. 3.1).
@@ -119,6 +126,18 @@ def c4(seed: int = 4, device="cpu", m: int = 1 << 20, n: int = 1024, k: int = 12
         N = torch.from_numpy(rng.standard_normal((i1 - i0, n))).to(dev)
         A[i0:i1] = (G1 @ G2 + noise * N).to(torch.float32)
     return A
+
+
+def c5_train(seed: int, device="cpu", n: int = 4096, dtype=torch.float64) -> torch.Tensor:
+    rng = np.random.default_rng(seed)
+    dev = torch.device(device)
+    s = torch.from_numpy(0.9 ** np.arange(64, dtype=np.float64)).to(dev)
+    Q1 = _haar_q(torch.from_numpy(rng.standard_normal((n, 64))).to(dev))
+    Q2 = _haar_q(torch.from_numpy(rng.standard_normal((n, 64))).to(dev))
+    sd = float(np.sqrt(1e-14 + 1e-12 / n))
+    A = (Q1 * s.unsqueeze(0)) @ Q2.T
+    A += sd * torch.from_numpy(rng.standard_normal((n, n))).to(dev)
+    return A.to(dtype)
 
 
 def hilbert(n: int) -> np.ndarray:

@@ -78,6 +78,32 @@ def test_select_option_errors_on_host(field, value, msg):
     assert msg in cur.last_error()
 
 
+@pytest.mark.parametrize("r,field,value,msg", [
+    (8, None, None, "ctx"), (65, None, None, "r <= 64"), (8, "col_block", 100, "col_block <= 64"),
+    (8, "method", 1, "maximal-volume"), (8, "mlp", None, "weight blob"),
+])
+def test_propose_option_errors_on_host(r, field, value, msg):
+    """The learned proposal's limits (r <= 64, leaf blocks of at most 64
+    columns, the maximal-volume method, a weight blob) are checked before any
+    device work; a valid request without a context fails on the context."""
+    o = cur.make_opts()
+    o.propose, o.mlp = 1, ctypes.c_void_p(1)
+    if field is not None:
+        setattr(o, field, value)
+    assert _sel(m=300, n=300, lda=300, r=r, opts=o) == cur.ERR_ARG
+    assert msg in cur.last_error()
+
+
+def test_feature_argument_errors_on_host():
+    L = cur.lib()
+    p = ctypes.c_void_p(1)
+    for r, w, msg in ((65, 0, "r <= 64"), (8, 100, "col_block <= 64"), (16, 8, "col_block must be >= r")):
+        assert L.cur_mlp_features(None, cur.F64, p, 300, 300, 300, r, w, 0, p) == cur.ERR_ARG
+        assert msg in cur.last_error()
+    assert L.cur_mlp_features(None, cur.F64, p, 300, 300, 300, 8, 0, 0, None) == cur.ERR_ARG
+    assert "F must" in cur.last_error()
+
+
 def test_null_context_is_an_argument_error():
     assert _sel() == cur.ERR_ARG
     assert "ctx" in cur.last_error()

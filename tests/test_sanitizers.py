@@ -46,7 +46,7 @@ def test_oracle_under_asan_ubsan(tmp_path):
 def test_abi_host_paths_under_asan_ubsan(tmp_path):
     objdir = os.path.join(PKG, "_build")
     others = [os.path.join(objdir, f"{s}.o") for s in ("select", "pass", "assemble", "residual", "residual_mp",
-                                                       "greedy")]
+                                                       "greedy", "propose")]
     if not all(os.path.exists(o) for o in others):
         pytest.skip("library objects not built (python -m paper_2502_11017_amd.build)")
     api = str(tmp_path / "api_san.o")
