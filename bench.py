@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_c2_traffic.json")
+TRAFFIC_FILE = {"pass": os.path.join(ROOT, "profiles", "pass_c2_traffic.json"),
+                "fresh": os.path.join(ROOT, "profiles", "fresh_c2_traffic.json")}
 PASS_SOURCE = os.path.join(ROOT, "paper_2502_11017_amd", "csrc", "pass.hip")
 
 
@@ -44,11 +45,12 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
-    or None when the pass kernel's source changed since it was taken."""
+def measured_traffic(kind):
+    """HBM bytes per launch of the pass (kind "pass") or fresh-B ("fresh")
+    kernel from the committed rocprofv3 counter summary, or None when their
+    source changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE[kind]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -222,6 +224,9 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of the launch autotuner cache: loaded before the run when it exists, "
                          "written at the end (profiling runs reuse the tuned launch shapes)")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="node groups (streams) per tree level of the C2 selection: 0 autotuned, 1 one stream "
+                         "(a single-stream kernel timeline), 2 or 3")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="one untimed device copy of this size, the calibration of the byte counters")
     args = ap.parse_args()
@@ -259,7 +264,7 @@ def main():
         del src, dst
 
     def step(Ax):
-        res = cur.select(Ax, r)
+        res = cur.select(Ax, r, groups=args.groups)
         C, U, R = cur.assemble(Ax, res["I"], res["J"])
         cheb, fro = cur.residual(Ax, C, U, R)
         return res, cheb, fro
@@ -328,9 +333,8 @@ def main():
 
     roof_pass, roof_fresh = roof("pass"), roof("fresh")
     pass_gbs = roof_pass["achieved"]
-    traffic = measured_traffic()
-    roof_pass["traffic"] = traffic
-    roof_fresh["traffic"] = None
+    roof_pass["traffic"] = measured_traffic("pass")
+    roof_fresh["traffic"] = measured_traffic("fresh")
 
     I = res["I"].cpu().numpy()
     J = res["J"].cpu().numpy()

@@ -1,4 +1,5 @@
-"""Build libcur.so (HIP, gfx950) in-tree with hipcc.
+"""Build libcur.so (HIP, gfx950) and the microbenchmark library libcurbench.so
+in-tree with hipcc.
 
 Usage: python -m paper_2502_11017_amd.build
 """
@@ -13,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcur.so")
+BENCH_LIB = os.path.join(HERE, "libcurbench.so")  # the microbenchmarks (not part of the selection ABI)
+BENCH_SOURCES = ["microbench.hip"]
 SOURCES = ["api.hip", "select.hip", "pass.hip", "assemble.hip", "residual.hip", "residual_mp.hip", "greedy.hip",
            "propose.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,9 +29,11 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
+    """Compiles libcur.so and libcurbench.so; returns the path of libcur.so."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
+    all_src = SOURCES + BENCH_SOURCES
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in all_src]
     failed = []
 
     def finish(src, p, log):
@@ -42,7 +47,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             sys.stdout.write(out.decode(errors="replace"))
 
     running = []  # at most `jobs` compilers at a time, each drained when it ends
-    for src, obj in zip(SOURCES, objs):
+    for src, obj in zip(all_src, objs):
         while len(running) >= jobs:
             done = [sp for sp in running if sp[1].poll() is not None]
             if not done:
@@ -62,10 +67,10 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         for src, out in failed:
             sys.stderr.write(f"--- {src}\n{out}\n")
         raise RuntimeError("hipcc failed for " + ", ".join(s for s, _ in failed))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    for lib, o in ((LIB, objs[:len(SOURCES)]), (BENCH_LIB, objs[len(SOURCES):])):
+        tmp = lib + ".tmp"
+        subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *o])
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -1,12 +1,28 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
     python -m paper_2502_11017_amd.profsum stats   STATS_CSV [--top N] [--match TEXT]
+    python -m paper_2502_11017_amd.profsum levels  TRACE_CSV [--skip N]
+    python -m paper_2502_11017_amd.profsum mfma    COUNTER_CSV [--match TEXT] [--simds N] [--ghz F]
     python -m paper_2502_11017_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
            --copy-bytes N --source FILE [--workload TEXT] [--command TEXT ...]
            [--last N] [--bench-line FILE]
 
 ``stats`` prints the kernel table of a ``--kernel-trace --stats`` run
 (calls, total and average duration per kernel).
+
+``levels`` splits a single-stream ``--kernel-trace`` timeline of selections
+into tree levels (a selection starts at its input scan ``k_amax``, a level at
+``k_panel_from_A`` or ``k_merge_init``) and prints, per level and averaged
+over the selections after ``--skip``, the wall time, the kernel time of the
+streaming pass, the fresh-B kernel and the controller, and the gaps between
+kernels (launch and host latency: wall minus kernel time).
+
+``mfma`` reads one ``--pmc`` run of the MFMA counters
+(SQ_INSTS_VALU_MFMA_MOPS_F64/_BF16/_F8, SQ_VALU_MFMA_BUSY_CYCLES,
+GRBM_GUI_ACTIVE) and prints per kernel the counted MFMA flops per dispatch
+(MOPS x 512), the rate over each dispatch's own duration, and the MFMA busy
+share: busy cycles summed over the SIMDs divided by (duration x clock x
+SIMDs), with the 2.4 GHz peak engine clock unless --ghz says otherwise.
 
 ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into
 HBM bytes per launch of one kernel and prints them as JSON.  Both counters
@@ -53,6 +69,100 @@ def kernel_stats(path, top=25, match=None):
         out.append(f"{'other kernels (not matching ' + repr(match) + ')':<70} "
                    f"{sum(int(r['Calls']) for r in rest):>7} {rt / 1e6:>10.3f} {'':>10} {rt / total:>7.1%}")
     out.append(f"{'all kernels':<70} {sum(int(r['Calls']) for r in rows + rest):>7} {total / 1e6:>10.3f}")
+    return "\n".join(out)
+
+
+_CLASSES = (("k_pass", "pass"), ("k_fresh", "fresh"), ("k_ctl", "ctl"))
+
+
+def _kclass(name):
+    for key, cls in _CLASSES:
+        if key + "<" in name or key + "(" in name:
+            return cls
+    return "other"
+
+
+def level_table(path, skip=0):
+    """Per-level averages over the selections of a single-stream trace."""
+    rows = sorted(_rows(path), key=lambda r: int(r["Start_Timestamp"]))
+    sels, cur_sel = [], None
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "k_amax" in name:
+            cur_sel = []
+            sels.append(cur_sel)
+        if cur_sel is None:
+            continue
+        if "k_panel_from_A" in name or "k_merge_init" in name:
+            cur_sel.append([])
+        if cur_sel:
+            cur_sel[-1].append((name, int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    sels = [s for s in sels[skip:] if s]
+    if not sels:
+        raise SystemExit("no selection in the trace")
+    nlev = min(len(s) for s in sels)
+    out = [f"{len(sels)} selection(s), {nlev} levels; times in ms per selection (average)",
+           f"{'level':>5} {'wall':>8} {'pass':>8} {'fresh':>8} {'ctl':>8} {'other':>8} {'gaps':>8} "
+           f"{'launches':>9} {'ctl avg us':>11}"]
+    tot = dict(wall=0.0, pass_=0.0, fresh=0.0, ctl=0.0, other=0.0, n=0.0, nctl=0.0)
+    for lv in range(nlev):
+        acc = dict(wall=0.0, pass_=0.0, fresh=0.0, ctl=0.0, other=0.0, n=0.0, nctl=0.0)
+        for s in sels:
+            ks = s[lv]
+            # the level ends where the next one starts (the last level: its last kernel before assembly)
+            acc["wall"] += (max(e for _, _, e in ks) - ks[0][1]) / 1e6
+            for name, b, e in ks:
+                c = _kclass(name)
+                acc["pass_" if c == "pass" else c] += (e - b) / 1e6
+                acc["nctl"] += c == "ctl"
+            acc["n"] += len(ks)
+        k = len(sels)
+        a = {key: v / k for key, v in acc.items()}
+        busy = a["pass_"] + a["fresh"] + a["ctl"] + a["other"]
+        for key in tot:
+            tot[key] += a[key]
+        out.append(f"{lv:>5} {a['wall']:>8.3f} {a['pass_']:>8.3f} {a['fresh']:>8.3f} {a['ctl']:>8.3f} "
+                   f"{a['other']:>8.3f} {a['wall'] - busy:>8.3f} {a['n']:>9.0f} "
+                   f"{1e3 * a['ctl'] / max(1.0, a['nctl']):>11.1f}")
+    busy = tot["pass_"] + tot["fresh"] + tot["ctl"] + tot["other"]
+    out.append(f"{'all':>5} {tot['wall']:>8.3f} {tot['pass_']:>8.3f} {tot['fresh']:>8.3f} {tot['ctl']:>8.3f} "
+               f"{tot['other']:>8.3f} {tot['wall'] - busy:>8.3f} {tot['n']:>9.0f} "
+               f"{1e3 * tot['ctl'] / max(1.0, tot['nctl']):>11.1f}")
+    return "\n".join(out)
+
+
+def mfma_table(path, match=None, simds=1024, ghz=2.4):
+    """Per kernel: dispatches, average duration, MFMA flops per dispatch by
+    type, the rate they give over the dispatch's own duration, and the MFMA
+    busy share: busy cycles summed over the SIMDs / (duration x clock x SIMDs).
+    (GRBM_GUI_ACTIVE is kept in the table but not used for the share: under
+    counter collection it spans the collection window, not the kernel.)"""
+    per = {}  # dispatch -> (name, duration ns, {counter: [values]})
+    for r in _rows(path):
+        if match and match not in r["Kernel_Name"]:
+            continue
+        d = int(r["Dispatch_Id"])
+        name, dur, cnt = per.setdefault(d, (r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), {}))
+        cnt.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    agg = {}
+    for name, dur, cnt in per.values():
+        a = agg.setdefault(name, dict(n=0, dur=0.0, f64=0.0, bf16=0.0, f8=0.0, busy=0.0))
+        a["n"] += 1
+        a["dur"] += dur
+        for key, ctr in (("f64", "SQ_INSTS_VALU_MFMA_MOPS_F64"), ("bf16", "SQ_INSTS_VALU_MFMA_MOPS_BF16"),
+                         ("f8", "SQ_INSTS_VALU_MFMA_MOPS_F8")):
+            a[key] += 512.0 * sum(cnt.get(ctr, [0.0]))
+        a["busy"] += sum(cnt.get("SQ_VALU_MFMA_BUSY_CYCLES", [0.0]))
+    out = [f"{'kernel':<52} {'disp':>4} {'avg us':>9} {'F64 GFLOP':>10} {'BF16 GFLOP':>11} {'F8 GFLOP':>9} "
+           f"{'TFLOP/s':>8} {'MFMA busy':>10}"]
+    for name, a in sorted(agg.items(), key=lambda kv: -kv[1]["busy"]):
+        n = a["n"]
+        short = name if len(name) <= 52 else name[:49] + "..."
+        flops = a["f64"] + a["bf16"] + a["f8"]
+        rate = flops / a["dur"] / 1e3 if a["dur"] > 0 else float("nan")
+        util = a["busy"] / (a["dur"] * ghz * simds) if a["dur"] > 0 else float("nan")
+        out.append(f"{short:<52} {n:>4} {a['dur'] / n / 1e3:>9.1f} {a['f64'] / n / 1e9:>10.3f} "
+                   f"{a['bf16'] / n / 1e9:>11.3f} {a['f8'] / n / 1e9:>9.3f} {rate:>8.1f} {util:>10.3f}")
     return "\n".join(out)
 
 
@@ -103,6 +213,14 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=25)
     s.add_argument("--match", default=None)
+    lv = sub.add_parser("levels")
+    lv.add_argument("csv")
+    lv.add_argument("--skip", type=int, default=0, help="selections to leave out at the start (warm-up)")
+    mf = sub.add_parser("mfma")
+    mf.add_argument("csv")
+    mf.add_argument("--match", default=None)
+    mf.add_argument("--simds", type=int, default=1024, help="SIMDs of the GPU (4 per compute unit)")
+    mf.add_argument("--ghz", type=float, default=2.4, help="engine clock for the busy share")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -114,15 +232,23 @@ def main(argv=None):
     t.add_argument("--last", type=int, default=0, help="average over the final N dispatches only")
     t.add_argument("--bench-line", default=None,
                    help="file holding the bench JSON line of the same run (its algorithmic bytes per launch)")
+    t.add_argument("--roof-key", default="roofline",
+                   help="the bench line's roofline record of this kernel (roofline: k_pass, roofline_fresh: k_fresh)")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(kernel_stats(a.csv, a.top, a.match))
+        return 0
+    if a.cmd == "levels":
+        print(level_table(a.csv, a.skip))
+        return 0
+    if a.cmd == "mfma":
+        print(mfma_table(a.csv, a.match, a.simds, a.ghz))
         return 0
     rec = pass_traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.last)
     if a.bench_line:
         with open(a.bench_line) as f:
             line = [ln for ln in f if ln.startswith("{")][-1]
-        roof = json.loads(line)["roofline"]
+        roof = json.loads(line)[a.roof_key]
         rec["algorithmic_bytes_per_launch_same_launches"] = roof["algorithmic_bytes_per_launch"]
         rec["traffic_over_algorithmic"] = rec["bytes_per_launch"] / roof["algorithmic_bytes_per_launch"]
     with open(a.source, "rb") as f:

@@ -44,3 +44,45 @@ def test_traffic_calibrated_by_the_copy_and_last_dispatches(tmp_path):
     last = profsum.pass_traffic(str(fp), str(wp), "k_pass", copy, last=1)
     assert last["launches"] == 1 and abs(last["bytes_per_launch"] - 2 * 300.0 * 1024) < 1e-6
     json.dumps(rec)
+
+
+def test_level_table_splits_selections_and_levels(tmp_path):
+    """Two selections of two levels each on one stream; the first is skipped.
+    Level 0 of the second: 0.010 ms wall starting at its panel copy, with
+    pass 2 us, fresh 1 us, ctl 3 us; level 1: the merge set-up and one ctl."""
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for base in (0, 1_000_000):
+        rows += [["void cur::k_amax<double>(...)", base, base + 1000],
+                 ["void cur::k_panel_from_A<double>(...)", base + 2000, base + 3000],
+                 ["void cur::k_fresh<double, 64>(...)", base + 4000, base + 5000],
+                 ["void cur::k_pass<double, 64>(...)", base + 5000, base + 7000],
+                 ["void cur::k_ctl<double, 64>(...)", base + 9000, base + 12000],
+                 ["cur::k_merge_init(...)", base + 20000, base + 21000],
+                 ["void cur::k_ctl<double, 64>(...)", base + 22000, base + 26000]]
+    p = tmp_path / "t.csv"
+    _write(p, hdr, rows)
+    out = profsum.level_table(str(p), skip=1).splitlines()
+    assert out[0].startswith("1 selection(s), 2 levels")
+    lv0 = out[2].split()
+    assert lv0[:7] == ["0", "0.010", "0.002", "0.001", "0.003", "0.001", "0.003"]
+    lv1 = out[3].split()
+    assert lv1[:7] == ["1", "0.006", "0.000", "0.000", "0.004", "0.001", "0.001"]
+    assert out[4].split()[0] == "all"
+
+
+def test_mfma_table_flops_and_busy_share(tmp_path):
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for d in (1, 2):
+        # two shader-engine instances of each SQ counter; a 1 ms dispatch
+        t0 = d * 10_000_000
+        for ctr, v in (("SQ_INSTS_VALU_MFMA_MOPS_F64", 1e6), ("SQ_VALU_MFMA_BUSY_CYCLES", 1.2288e9 / 2)):
+            rows += [[d, "k_resid_mfma<double>", ctr, v, t0, t0 + 1_000_000]] * 2
+        rows += [[d, "k_resid_mfma<double>", "GRBM_GUI_ACTIVE", 7e6, t0, t0 + 1_000_000]]
+    p = tmp_path / "c.csv"
+    _write(p, hdr, rows)
+    f = profsum.mfma_table(str(p), simds=1024, ghz=2.4).splitlines()[1].split()
+    assert f[1] == "2" and f[2] == "1000.0" and f[3] == "1.024"  # 2e6 MOPS x 512 per dispatch
+    assert f[-2] == "1.0"  # 1.024 GFLOP in 1 ms
+    assert f[-1] == "0.500"  # 1.2288e9 busy cycles / (1e6 ns x 2.4 GHz x 1024 SIMDs)
