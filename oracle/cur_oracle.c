@@ -16,6 +16,8 @@
  *   - Adaptive Cross Approximation with complete pivoting         (Alg. 1)
  *   - column blocks, per-block local maxima, global maximum        (Alg. 3)
  *   - Frobenius relative error                                     (Sec. 3.1)
+ *   - rectangular cross: r rows, c columns chosen independently,
+ *     U = A(I,J)^+ (c x r)                          (Alg. 2 inputs, Sec. 1.1)
  * The maxvol swap rule itself is only cited by the paper (Sec. 1.2, the
  * maximal-volume reference); it is written here from the Sherman-Morrison
  * identity.  The binary-tree merge is the partition-and-merge reading of the
@@ -838,6 +840,151 @@ int oracle_cur_residual(const double* A, int64_t m, int64_t n, int64_t lda, int 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Rectangular cross: r rows, c columns (Alg. 2 takes the two counts apart;  */
+/* Sec. 1.1 and the overview define U as the pseudo-inverse of A(I,J))       */
+/* ------------------------------------------------------------------------ */
+/*
+ * Pseudo-inverse of the p x q row-major G, written q x p row-major to P, by
+ * one-sided (Hestenes) Jacobi on the columns of the taller of G and G^T:
+ * for p >= q, W = G V with cyclic sweeps over column pairs (a < b) until
+ * every pair is orthogonal to 2^-52 relative (at most 60 sweeps), sigma_j =
+ * ||W(:,j)||, G^+ = V diag(1/sigma^2) W^T over sigma_j > max(p,q) 2^-52
+ * sigma_max; for p < q, G^+ = ((G^T)^+)^T.  Sums run over the rows in
+ * ascending order, one fma per term.  For p == q these are the operations of
+ * oracle_pinv.
+ */
+void oracle_pinv_rect(int p, int q, const double* G, double* P) {
+  if (p < q) {
+    double* T = (double*)malloc(sizeof(double) * (size_t)p * q);
+    double* Q = (double*)malloc(sizeof(double) * (size_t)p * q);
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < q; ++b) T[(size_t)b * p + a] = G[(size_t)a * q + b];
+    oracle_pinv_rect(q, p, T, Q); /* Q = (G^T)^+, p x q */
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < q; ++b) P[(size_t)b * p + a] = Q[(size_t)a * q + b];
+    free(T);
+    free(Q);
+    return;
+  }
+  double* W = (double*)malloc(sizeof(double) * (size_t)p * q);
+  double* V = (double*)malloc(sizeof(double) * (size_t)q * q);
+  double* sg = (double*)malloc(sizeof(double) * (size_t)q);
+  memcpy(W, G, sizeof(double) * (size_t)p * q);
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b) V[(size_t)a * q + b] = (a == b) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int a = 0; a < q - 1; ++a)
+      for (int b = a + 1; b < q; ++b) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = 0; i < p; ++i) {
+          double wa = W[(size_t)i * q + a], wb = W[(size_t)i * q + b];
+          al = fma(wa, wa, al);
+          be = fma(wb, wb, be);
+          ga = fma(wa, wb, ga);
+        }
+        if (ga == 0.0 || fabs(ga) <= 0x1p-52 * sqrt(al * be)) continue;
+        rotated = 1;
+        double zeta = (be - al) / (2.0 * ga);
+        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double cs = 1.0 / sqrt(1.0 + t * t);
+        double sn = cs * t;
+        for (int i = 0; i < p; ++i) {
+          double wa = W[(size_t)i * q + a], wb = W[(size_t)i * q + b];
+          W[(size_t)i * q + a] = cs * wa - sn * wb;
+          W[(size_t)i * q + b] = sn * wa + cs * wb;
+        }
+        for (int i = 0; i < q; ++i) {
+          double va = V[(size_t)i * q + a], vb = V[(size_t)i * q + b];
+          V[(size_t)i * q + a] = cs * va - sn * vb;
+          V[(size_t)i * q + b] = sn * va + cs * vb;
+        }
+      }
+    if (!rotated) break;
+  }
+  double smax = 0.0;
+  for (int j = 0; j < q; ++j) {
+    double sum = 0.0;
+    for (int i = 0; i < p; ++i) sum = fma(W[(size_t)i * q + j], W[(size_t)i * q + j], sum);
+    sg[j] = sqrt(sum);
+    if (sg[j] > smax) smax = sg[j];
+  }
+  const double cut = (double)p * 0x1p-52 * smax;
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < p; ++b) {
+      double sum = 0.0;
+      for (int j = 0; j < q; ++j) {
+        if (!(sg[j] > cut)) continue;
+        sum = fma(V[(size_t)a * q + j], W[(size_t)b * q + j] / (sg[j] * sg[j]), sum);
+      }
+      P[(size_t)a * p + b] = sum;
+    }
+  free(W);
+  free(V);
+  free(sg);
+}
+
+/*
+ * C = A(:,J) (m x c), R = A(I,:) (r x n), U = A(I,J)^+ (c x r) by
+ * oracle_pinv_rect, all row-major FP64.  I holds r rows, J c columns.
+ */
+int oracle_cur_assemble_rect(const double* A, int64_t m, int64_t n, int64_t lda, int r, int c,
+                             const int64_t* I, const int64_t* J, double* C, double* U, double* R) {
+  if (!A || !I || !J || !C || !U || !R || m < 1 || n < 1 || lda < n || r < 1 || c < 1 || (int64_t)r > m ||
+      (int64_t)c > n)
+    return ORC_ERR_ARG;
+  for (int k = 0; k < r; ++k)
+    if (I[k] < 0 || I[k] >= m) return ORC_ERR_ARG;
+  for (int k = 0; k < c; ++k)
+    if (J[k] < 0 || J[k] >= n) return ORC_ERR_ARG;
+  for (int64_t i = 0; i < m; ++i)
+    for (int k = 0; k < c; ++k) C[i * c + k] = A[i * lda + J[k]];
+  for (int k = 0; k < r; ++k)
+    for (int64_t j = 0; j < n; ++j) R[(int64_t)k * n + j] = A[I[k] * lda + j];
+  double* G = (double*)malloc(sizeof(double) * (size_t)r * c);
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < c; ++b) G[(size_t)a * c + b] = A[I[a] * lda + J[b]];
+  oracle_pinv_rect(r, c, G, U);
+  free(G);
+  return ORC_OK;
+}
+
+/*
+ * Residual of the rectangular form: Bm = C U (m x r, sums over l < c
+ * ascending), E(i,j) = A(i,j) - sum_k Bm(i,k) R(k,j) (k < r ascending);
+ * cheb, fro_rel and the non-finite verdict as in oracle_cur_residual.  C is
+ * m x c, U c x r, R r x n.
+ */
+int oracle_cur_residual_rect(const double* A, int64_t m, int64_t n, int64_t lda, int r, int c, const double* C,
+                             const double* U, const double* R, double* cheb, double* fro_rel) {
+  if (!A || !C || !U || !R || !cheb || m < 1 || n < 1 || lda < n || r < 1 || c < 1) return ORC_ERR_ARG;
+  double* Bm = (double*)malloc(sizeof(double) * (size_t)r);
+  double emax = 0.0, esq = 0.0, asq = 0.0;
+  int nonfinite = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    for (int k = 0; k < r; ++k) {
+      double sum = 0.0;
+      for (int l = 0; l < c; ++l) sum = fma(C[i * c + l], U[(size_t)l * r + k], sum);
+      Bm[k] = sum;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      double sum = 0.0;
+      for (int k = 0; k < r; ++k) sum = fma(Bm[k], R[(int64_t)k * n + j], sum);
+      double a = A[i * lda + j];
+      double e = a - sum;
+      if (!isfinite(e)) nonfinite = 1;
+      else if (fabs(e) > emax) emax = fabs(e);
+      esq = fma(e, e, esq);
+      asq = fma(a, a, asq);
+    }
+  }
+  free(Bm);
+  *cheb = nonfinite ? NAN : emax;
+  if (fro_rel) *fro_rel = (asq > 0.0) ? sqrt(esq) / sqrt(asq) : 0.0;
+  return nonfinite ? ORC_ERR_NONFINITE : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Norm-greedy selection (Alg. 2 with Alg. 3)                                */
 /* ------------------------------------------------------------------------ */
 /*
@@ -858,6 +1005,10 @@ int oracle_cur_residual(const double* A, int64_t m, int64_t n, int64_t lda, int 
  * ascending index order, one fma per element, as the definition reads.  The
  * update of an element is one fma with the coefficient c = (s . v) / (s . s).
  */
+int oracle_greedy_select_rc(const double* A, int64_t m, int64_t n, int64_t lda, int r, int c, int64_t* order_I,
+                            int64_t* order_J, int64_t* I, int64_t* J, int* rank_rows, int* rank_cols,
+                            double* gap_I, double* gap_J);
+
 static double plain_dot(const double* a, const double* b, int64_t len) {
   double s = 0.0;
   for (int64_t i = 0; i < len; ++i) s = fma(a[i], b[i], s);
@@ -924,17 +1075,28 @@ static int greedy_axis(double* W, int64_t len, int64_t cnt, int r, int64_t* orde
 int oracle_greedy_select(const double* A, int64_t m, int64_t n, int64_t lda, int r, int64_t* order_I,
                          int64_t* order_J, int64_t* I, int64_t* J, int* rank_rows, int* rank_cols,
                          double* gap_I, double* gap_J) {
-  if (!A || m < 1 || n < 1 || lda < n || r < 1 || r > m || r > n) return ORC_ERR_ARG;
+  return oracle_greedy_select_rc(A, m, n, lda, r, r, order_I, order_J, I, J, rank_rows, rank_cols, gap_I, gap_J);
+}
+
+/*
+ * The same with a row count r and a column count c (Alg. 2 takes the two
+ * separately): order_I / I hold r entries, order_J / J hold c.
+ */
+int oracle_greedy_select_rc(const double* A, int64_t m, int64_t n, int64_t lda, int r, int c, int64_t* order_I,
+                            int64_t* order_J, int64_t* I, int64_t* J, int* rank_rows, int* rank_cols,
+                            double* gap_I, double* gap_J) {
+  if (!A || m < 1 || n < 1 || lda < n || r < 1 || c < 1 || r > m || c > n || r > n || c > m) return ORC_ERR_ARG;
   double* W = (double*)malloc(sizeof(double) * (size_t)(m * n));
   if (!W) return ORC_ERR_NOMEM;
-  for (int64_t i = 0; i < r; ++i) order_I[i] = order_J[i] = I[i] = J[i] = -1;
+  for (int64_t i = 0; i < r; ++i) order_I[i] = I[i] = -1;
+  for (int64_t j = 0; j < c; ++j) order_J[j] = J[j] = -1;
   /* rows: vector i = A(i, :) */
   for (int64_t i = 0; i < m; ++i) memcpy(W + i * n, A + i * lda, sizeof(double) * (size_t)n);
   const int qr = greedy_axis(W, n, m, r, order_I, gap_I);
   /* columns: vector j = A(:, j) */
   for (int64_t i = 0; i < m; ++i)
     for (int64_t j = 0; j < n; ++j) W[j * m + i] = A[i * lda + j];
-  const int qc = greedy_axis(W, m, n, r, order_J, gap_J);
+  const int qc = greedy_axis(W, m, n, c, order_J, gap_J);
   free(W);
   for (int t = 0; t < qr; ++t) I[t] = order_I[t];
   for (int t = 0; t < qc; ++t) J[t] = order_J[t];
@@ -942,5 +1104,5 @@ int oracle_greedy_select(const double* A, int64_t m, int64_t n, int64_t lda, int
   sort_i64(J, qc);
   *rank_rows = qr;
   *rank_cols = qc;
-  return (qr < r || qc < r) ? ORC_ERR_RANK : ORC_OK;
+  return (qr < r || qc < c) ? ORC_ERR_RANK : ORC_OK;
 }

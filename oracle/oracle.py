@@ -79,6 +79,14 @@ def lib():
         L.oracle_cur_residual.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P]
         L.oracle_cur_residual.restype = i32
         L.oracle_greedy_select.argtypes = [P, i64, i64, i64, i32, P, P, P, P, P, P, P, P]
+        L.oracle_greedy_select_rc.argtypes = [P, i64, i64, i64, i32, i32, P, P, P, P, P, P, P, P]
+        L.oracle_greedy_select_rc.restype = i32
+        L.oracle_pinv_rect.argtypes = [i32, i32, P, P]
+        L.oracle_pinv_rect.restype = None
+        L.oracle_cur_assemble_rect.argtypes = [P, i64, i64, i64, i32, i32, P, P, P, P, P]
+        L.oracle_cur_assemble_rect.restype = i32
+        L.oracle_cur_residual_rect.argtypes = [P, i64, i64, i64, i32, i32, P, P, P, P, P]
+        L.oracle_cur_residual_rect.restype = i32
         L.oracle_greedy_select.restype = i32
         _lib = L
     return _lib
@@ -302,3 +310,80 @@ def greedy(A, r):
         raise ValueError("oracle_greedy_select: invalid argument")
     return {"order_I": oI, "order_J": oJ, "I": I, "J": J, "status": st, "rank_rows": qr.value,
             "rank_cols": qc.value, "gap_I": gI, "gap_J": gJ}
+
+
+# ---------------------------------------------------------------- rectangular cross (r rows, c columns)
+def pinv_rect(G):
+    """G^+ (q x p) of the p x q G by oracle_pinv_rect."""
+    G = _f64(G)
+    p, q = G.shape
+    P = np.zeros((q, p))
+    lib().oracle_pinv_rect(p, q, _p(G), _p(P))
+    return P
+
+
+def assemble_rect(A, I, J):
+    """C = A(:,J) (m x c), U = A(I,J)^+ (c x r), R = A(I,:) (r x n)."""
+    A = _f64(A)
+    m, n = A.shape
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    r, c = len(I), len(J)
+    C, U, R = np.zeros((m, c)), np.zeros((c, r)), np.zeros((r, n))
+    rc = lib().oracle_cur_assemble_rect(_p(A), m, n, n, r, c, _p(I), _p(J), _p(C), _p(U), _p(R))
+    if rc != OK:
+        raise ValueError(f"oracle_cur_assemble_rect: {rc}")
+    return C, U, R
+
+
+def residual_rect(A, C, U, R):
+    """(cheb, fro_rel) of A - (C U) R for C m x c, U c x r, R r x n."""
+    A, C, U, R = _f64(A), _f64(C), _f64(U), _f64(R)
+    m, n = A.shape
+    c, r = U.shape
+    cheb, fro = ctypes.c_double(), ctypes.c_double()
+    rc = lib().oracle_cur_residual_rect(_p(A), m, n, n, r, c, _p(C), _p(U), _p(R), ctypes.byref(cheb),
+                                        ctypes.byref(fro))
+    if rc not in (OK, ERR_NONFINITE):
+        raise ValueError(f"oracle_cur_residual_rect: {rc}")
+    return cheb.value, fro.value
+
+
+def greedy_rc(A, r, c):
+    """Norm-greedy rows (r) and columns (c), oracle_greedy_select_rc."""
+    A = _f64(A)
+    m, n = A.shape
+    oI, I = np.full(r, -1, np.int64), np.full(r, -1, np.int64)
+    oJ, J = np.full(c, -1, np.int64), np.full(c, -1, np.int64)
+    qr, qc = ctypes.c_int(0), ctypes.c_int(0)
+    st = lib().oracle_greedy_select_rc(_p(A), m, n, n, r, c, _p(oI), _p(oJ), _p(I), _p(J), ctypes.byref(qr),
+                                       ctypes.byref(qc), None, None)
+    if st == ERR_ARG:
+        raise ValueError("oracle_greedy_select_rc: invalid argument")
+    return {"order_I": oI, "order_J": oJ, "I": I, "J": J, "status": st, "rank_rows": qr.value,
+            "rank_cols": qc.value}
+
+
+def _worse(a, b):
+    """The combined status of two selections: a rank shortfall, then a spent
+    swap budget, then OK."""
+    for s in (ERR_RANK, WARN_NOCONV):
+        if s in (a, b):
+            return s
+    return a if a != OK else b
+
+
+def select_rect(A, r, c, method=0, w=0, tau=0.0, max_swaps=0):
+    """Alg. 2 with separate counts: I (r rows) and J (c columns) chosen
+    independently, each along its own axis.  method 0: J by the column-block
+    maximal-volume tree on A with rank c, I by the same tree on A^T (row
+    blocks of A) with rank r -- each tree's other index set is dropped;
+    method 1: the norm-greedy rule on rows and on columns (greedy_rc)."""
+    A = _f64(A)
+    if method == 1:
+        g = greedy_rc(A, r, c)
+        return {"I": g["I"], "J": g["J"], "status": g["status"]}
+    cols = select(A, c, w=w, tau=tau, max_swaps=max_swaps)
+    rows = select(np.ascontiguousarray(A.T), r, w=w, tau=tau, max_swaps=max_swaps)
+    return {"I": rows["J"], "J": cols["J"], "status": _worse(rows["status"], cols["status"]),
+            "rows": rows, "cols": cols}
