@@ -226,6 +226,37 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
                               cur_status* per_item);
 
 /*
+ * Rectangular cross (Alg. 2 takes a row count r and a column count c and
+ * chooses I and J independently, each along its own axis; Sec. 1.1 and the
+ * overview define U as the pseudo-inverse of A(I,J)).
+ *
+ * cur_select_rect: I (device int64[r], ascending) and J (device int64[c],
+ * ascending).  opts->method 0: J from the column-block maximal-volume tree on
+ * A with rank c, I from the same tree on A^T (the row blocks of A) with rank
+ * r, each tree's other index set dropped; col_block (0 -> max(64, r, c), and
+ * >= max(r, c)), tau, max_swaps and groups apply to both trees.  method 1: the
+ * norm-greedy rule (Alg. 3) on rows (r) and on columns (c).  Requires
+ * 1 <= r, c <= min(m, n) and r, c <= 128; no trace, no learned proposal.
+ * Status: CUR_ERR_RANK if either axis is rank-short (entries past the rank
+ * reached are -1), else CUR_WARN_NOCONV if either tree spent its swap budget.
+ * info (nullable): rank = the smaller of the two ranks reached, swaps /
+ * phases / refreshes / nodes summed over both trees, logvol NaN.
+ */
+cur_status cur_select_rect(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,
+                           int32_t c, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info);
+/* C = A(:,J) (device, m x c row-major, element dtype), R = A(I,:) (r x n),
+ * U = A(I,J)^+ (device FP64, c x r row-major) by one-sided Jacobi on the
+ * taller of A(I,J) and its transpose, cut-off max(r, c) 2^-52 sigma_max.
+ * Requires min(r, c) <= 64 and max(r, c) <= 128. */
+cur_status cur_assemble_rect(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                             int32_t r, int32_t c, const int64_t* I, const int64_t* J, void* C, double* U, void* R);
+/* Residual max |A - C U R| and ||A - C U R||_F / ||A||_F of the factors of
+ * cur_assemble_rect (C m x c, U c x r, R r x n), in the input's arithmetic
+ * (FP64 products on MFMA); CUR_ERR_NONFINITE as for cur_residual. */
+cur_status cur_residual_rect(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,
+                             int32_t c, const void* C, const double* U, const void* R, double* cheb, double* fro_rel);
+
+/*
  * Learned candidate proposal (cur_opts.propose = 1).
  * A small MLP scores every row of every leaf block from four features; the
  * leaf's 4r best rows are the candidates of a restricted start (adaptive

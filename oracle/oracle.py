@@ -356,12 +356,13 @@ def greedy_rc(A, r, c):
     oI, I = np.full(r, -1, np.int64), np.full(r, -1, np.int64)
     oJ, J = np.full(c, -1, np.int64), np.full(c, -1, np.int64)
     qr, qc = ctypes.c_int(0), ctypes.c_int(0)
+    gI, gJ = np.full(r, np.nan), np.full(c, np.nan)
     st = lib().oracle_greedy_select_rc(_p(A), m, n, n, r, c, _p(oI), _p(oJ), _p(I), _p(J), ctypes.byref(qr),
-                                       ctypes.byref(qc), None, None)
+                                       ctypes.byref(qc), _p(gI), _p(gJ))
     if st == ERR_ARG:
         raise ValueError("oracle_greedy_select_rc: invalid argument")
     return {"order_I": oI, "order_J": oJ, "I": I, "J": J, "status": st, "rank_rows": qr.value,
-            "rank_cols": qc.value}
+            "rank_cols": qc.value, "gap_I": gI, "gap_J": gJ}
 
 
 def _worse(a, b):
@@ -382,7 +383,7 @@ def select_rect(A, r, c, method=0, w=0, tau=0.0, max_swaps=0):
     A = _f64(A)
     if method == 1:
         g = greedy_rc(A, r, c)
-        return {"I": g["I"], "J": g["J"], "status": g["status"]}
+        return {"I": g["I"], "J": g["J"], "status": g["status"], "greedy": g}
     cols = select(A, c, w=w, tau=tau, max_swaps=max_swaps)
     rows = select(np.ascontiguousarray(A.T), r, w=w, tau=tau, max_swaps=max_swaps)
     return {"I": rows["J"], "J": cols["J"], "status": _worse(rows["status"], cols["status"]),

@@ -109,6 +109,14 @@ def lib():
         L.cur_residual.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, i32,
                                    ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.cur_residual.restype = ctypes.c_int
+        L.cur_select_rect.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, i32, ctypes.POINTER(Opts), P, P,
+                                      ctypes.POINTER(Info)]
+        L.cur_select_rect.restype = ctypes.c_int
+        L.cur_assemble_rect.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, i32, P, P, P, P, P]
+        L.cur_assemble_rect.restype = ctypes.c_int
+        L.cur_residual_rect.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, i32, P, P, P,
+                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.cur_residual_rect.restype = ctypes.c_int
         L.cur_residual_noalloc.argtypes = [P, ctypes.c_int, P, i64, i64, i64, i32, P, P, P, i32,
                                            ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.cur_residual_noalloc.restype = ctypes.c_int
@@ -281,6 +289,57 @@ def residual(A, C, U, R, prec: int = PREC_NATIVE):
     rc = lib().cur_residual(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
                             ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
                             ctypes.c_void_p(R.data_ptr()), int(prec), ctypes.byref(cheb), ctypes.byref(fro))
+    _check(rc)
+    return cheb.value, fro.value
+
+
+def select_rect(A, r: int, c: int, method: int = METHOD_MAXVOL, col_block: int = 0, tau: float = 0.0,
+                max_swaps: int = 0, groups: int = 0, allow=(OK, WARN_NOCONV, ERR_RANK)):
+    """r rows I and c columns J chosen independently (Alg. 2), cur_select_rect."""
+    torch = _torch()
+    m, n, lda = _matrix(A)
+    ctx = context(A.device.index)
+    I = torch.empty(r, dtype=torch.int64, device=A.device)
+    J = torch.empty(c, dtype=torch.int64, device=A.device)
+    info = Info()
+    o = make_opts(col_block, tau, max_swaps, groups=groups, method=method)
+    rc = lib().cur_select_rect(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r, c,
+                               ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                               ctypes.byref(info))
+    _check(rc, allow)
+    return {"I": I, "J": J, "status": rc, "rank": info.rank, "nodes": info.nodes, "phases": info.phases,
+            "refreshes": info.refreshes, "swaps": info.swaps}
+
+
+def assemble_rect(A, I, J):
+    """C = A(:,J) (m x c), U = A(I,J)^+ (c x r, FP64), R = A(I,:) (r x n), cur_assemble_rect."""
+    torch = _torch()
+    m, n, lda = _matrix(A)
+    r, c = int(I.numel()), int(J.numel())
+    ctx = context(A.device.index)
+    C = torch.empty((m, c), dtype=A.dtype, device=A.device)
+    U = torch.empty((c, r), dtype=torch.float64, device=A.device)
+    R = torch.empty((r, n), dtype=A.dtype, device=A.device)
+    I = I.to(torch.int64).contiguous()
+    J = J.to(torch.int64).contiguous()
+    rc = lib().cur_assemble_rect(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r, c,
+                                 ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                                 ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(R.data_ptr()))
+    _check(rc)
+    return C, U, R
+
+
+def residual_rect(A, C, U, R):
+    """(max|A - CUR|, ||A - CUR||_F / ||A||_F) of a rectangular cross, cur_residual_rect."""
+    m, n, lda = _matrix(A)
+    c, r = int(U.shape[0]), int(U.shape[1])
+    ctx = context(A.device.index)
+    C, U, R = C.contiguous(), U.contiguous(), R.contiguous()
+    cheb, fro = ctypes.c_double(), ctypes.c_double()
+    rc = lib().cur_residual_rect(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r, c,
+                                 ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(R.data_ptr()), ctypes.byref(cheb), ctypes.byref(fro))
     _check(rc)
     return cheb.value, fro.value
 

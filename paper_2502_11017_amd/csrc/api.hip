@@ -157,6 +157,7 @@ cur_status cur_create(cur_ctx* out, int device, void* hip_stream) {
   c->arena = nullptr;
   c->arena_bytes = 0;
   c->last_pinv = 0;
+  c->rect_discard = nullptr;
   c->prof_on = 0;
   c->prof_bytes = nullptr;
   c->prof_ev = new std::vector<hipEvent_t>();
@@ -197,6 +198,7 @@ cur_status cur_destroy(cur_ctx ctx) {
   if (ctx->host_flag) hipHostFree(ctx->host_flag);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   if (ctx->prof_bytes) hipFree(ctx->prof_bytes);
+  if (ctx->rect_discard) hipFree(ctx->rect_discard);
   for (hipEvent_t e : *ctx->prof_ev) hipEventDestroy(e);
   if (ctx->groups_ready) {
     for (int g = 0; g < 4; ++g) {
@@ -284,6 +286,71 @@ cur_status cur_residual_noalloc(cur_ctx ctx, int32_t dtype_in, const void* A, in
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
   return residual_noalloc_dispatch(ctx, dtype, A, m, n, lda, r, C, U, R, prec, cheb, fro_rel);
+}
+
+// ---- rectangular cross: r rows, c columns
+static cur_status check_rect(int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t c) {
+  cur_status st = check_matrix(dtype, A, m, n, lda, 1);
+  if (st != CUR_OK) return st;
+  const int64_t mn = std::min(m, n);
+  if (r < 1 || c < 1 || r > mn || c > mn) return arg_error("r and c must satisfy 1 <= r, c <= min(m, n)");
+  if (r > 128 || c > 128) return arg_error("r, c > 128 are not supported (kernels are instantiated for <= 128)");
+  return CUR_OK;
+}
+
+cur_status cur_select_rect(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,
+                           int32_t c, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info) {
+  cur_status st = check_rect(dtype_in, A, m, n, lda, r, c);
+  if (st != CUR_OK) return st;
+  const cur_dtype dtype = (cur_dtype)dtype_in;
+  st = check_select_rows(dtype, std::max(m, n));  // the row tree runs on A^T (n rows)
+  if (st != CUR_OK) return st;
+  if (!I || !J) return arg_error("I and J must be non-NULL device pointers");
+  cur_opts o;
+  st = resolve_opts(opts, dtype, std::max(r, c), n, &o);  // the leaf width must hold either rank
+  if (st != CUR_OK) return st;
+  if (o.trace) return arg_error("cur_select_rect takes no trace");
+  if (o.propose != 0) return arg_error("cur_select_rect takes no learned proposal");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  if (o.method == 1) return greedy_rect_dispatch(ctx, dtype, A, m, n, lda, r, c, I, J, info);
+  if (!ctx->rect_discard) CUR_HIP_CHECK(hipMalloc(&ctx->rect_discard, 256 * sizeof(int64_t)));
+  return select_rect_dispatch(ctx, dtype, A, m, n, lda, r, c, o, I, J, ctx->rect_discard, info);
+}
+
+cur_status cur_assemble_rect(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda,
+                             int32_t r, int32_t c, const int64_t* I, const int64_t* J, void* C, double* U, void* R) {
+  cur_status st = check_rect(dtype_in, A, m, n, lda, r, c);
+  if (st != CUR_OK) return st;
+  if (std::min(r, c) > 64) return arg_error("cur_assemble_rect needs min(r, c) <= 64");
+  const cur_dtype dtype = (cur_dtype)dtype_in;
+  if (!I || !J || !C || !U || !R) return arg_error("I, J, C, U and R must be non-NULL device pointers");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  std::vector<int64_t> hI(r), hJ(c);
+  CUR_HIP_CHECK(hipMemcpyAsync(hI.data(), I, sizeof(int64_t) * r, hipMemcpyDeviceToHost, ctx->stream));
+  CUR_HIP_CHECK(hipMemcpyAsync(hJ.data(), J, sizeof(int64_t) * c, hipMemcpyDeviceToHost, ctx->stream));
+  CUR_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < r; ++k)
+    if (hI[k] < 0 || hI[k] >= m) return arg_error("I entry out of range");
+  for (int k = 0; k < c; ++k)
+    if (hJ[k] < 0 || hJ[k] >= n) return arg_error("J entry out of range");
+  set_error("");
+  return assemble_rect_dispatch(ctx, dtype, A, m, n, lda, r, c, I, J, C, U, R);
+}
+
+cur_status cur_residual_rect(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda,
+                             int32_t r, int32_t c, const void* C, const double* U, const void* R, double* cheb,
+                             double* fro_rel) {
+  cur_status st = check_rect(dtype_in, A, m, n, lda, r, c);
+  if (st != CUR_OK) return st;
+  if (!C || !U || !R) return arg_error("C, U and R must be non-NULL device pointers");
+  if (!cheb) return arg_error("cheb must be a non-NULL host pointer");
+  if (!ctx) return arg_error("ctx is NULL");
+  CUR_HIP_CHECK(hipSetDevice(ctx->device));
+  set_error("");
+  return residual_rect_dispatch(ctx, (cur_dtype)dtype_in, A, m, n, lda, r, c, C, U, R, cheb, fro_rel);
 }
 
 cur_status cur_mlp_features(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,

@@ -199,6 +199,128 @@ static cur_status assemble_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
   return CUR_OK;
 }
 
+// ---------------------------------------------------------------- rectangular cross
+// U = A(I,J)^+ for r rows and c columns (c x r, row-major), one block: the
+// one-sided Jacobi pseudo-inverse on the taller of G = A(I,J) and G^T
+// (p x q, p >= q, p <= 128, q <= 64), W and V held in LDS.  Cyclic sweeps over
+// column pairs (a < b) in order; thread 0 forms the pair's three sums over
+// the p rows ascending (one fma per term) and the rotation, the block
+// rotates the rows of W and V; sigma_j = ||W(:,j)||, G^+ = V diag(1/sigma^2)
+// W^T over sigma_j > p 2^-52 sigma_max.  These are the oracle's operations
+// in its order, so U is reproduced bit for bit.
+constexpr int kPinvP = 128, kPinvQ = 64;
+struct PinvLds {
+  double W[kPinvP * kPinvQ];
+  double V[kPinvQ * kPinvQ];
+  double sg[kPinvQ];
+  double cs[3];
+  int rot;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pinv_rect(const T* __restrict__ A, int64_t lda, int r, int c,
+                                                        const int64_t* __restrict__ I, const int64_t* __restrict__ J,
+                                                        double* __restrict__ U) {
+  __shared__ PinvLds L;
+  const int tid = threadIdx.x;
+  const bool tall = r >= c;  // G (r x c) itself, else its transpose
+  const int p = tall ? r : c, q = tall ? c : r;
+  for (int idx = tid; idx < p * q; idx += kThreads) {
+    const int i = idx / q, j = idx % q;  // W(i, j) = G(i, j), or G(j, i)
+    L.W[idx] = tall ? (double)A[I[i] * lda + J[j]] : (double)A[I[j] * lda + J[i]];
+  }
+  for (int idx = tid; idx < q * q; idx += kThreads) L.V[idx] = (idx / q == idx % q) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) L.rot = 0;
+    __syncthreads();
+    for (int a = 0; a < q - 1; ++a)
+      for (int b = a + 1; b < q; ++b) {
+        if (tid == 0) {
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = 0; i < p; ++i) {
+            const double wa = L.W[i * q + a], wb = L.W[i * q + b];
+            al = fma(wa, wa, al);
+            be = fma(wb, wb, be);
+            ga = fma(wa, wb, ga);
+          }
+          L.cs[0] = 0.0;
+          L.cs[1] = 0.0;
+          if (!(ga == 0.0 || fabs(ga) <= 0x1p-52 * sqrt(al * be))) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cc = 1.0 / sqrt(1.0 + t * t);
+            L.cs[0] = cc;
+            L.cs[1] = cc * t;
+            L.rot = 1;
+          }
+        }
+        __syncthreads();
+        const double cc = L.cs[0], sn = L.cs[1];
+        if (cc != 0.0) {
+          for (int i = tid; i < p; i += kThreads) {
+            const double wa = L.W[i * q + a], wb = L.W[i * q + b];
+            L.W[i * q + a] = cc * wa - sn * wb;
+            L.W[i * q + b] = sn * wa + cc * wb;
+          }
+          for (int i = tid; i < q; i += kThreads) {
+            const double va = L.V[i * q + a], vb = L.V[i * q + b];
+            L.V[i * q + a] = cc * va - sn * vb;
+            L.V[i * q + b] = sn * va + cc * vb;
+          }
+        }
+        __syncthreads();
+      }
+    const int rot = L.rot;
+    __syncthreads();  // every wavefront has read the flag before it is reset
+    if (!rot) break;
+  }
+  if (tid == 0) {
+    double smax = 0.0;
+    for (int j = 0; j < q; ++j) {
+      double sum = 0.0;
+      for (int i = 0; i < p; ++i) sum = fma(L.W[i * q + j], L.W[i * q + j], sum);
+      L.sg[j] = sqrt(sum);
+      smax = fmax(smax, L.sg[j]);
+    }
+    L.cs[2] = (double)p * 0x1p-52 * smax;
+  }
+  __syncthreads();
+  const double cut = L.cs[2];
+  // P = W^+ of the working orientation (q x p); U = P (tall) or P^T
+  for (int idx = tid; idx < q * p; idx += kThreads) {
+    const int a = idx / p, b = idx % p;
+    double sum = 0.0;
+    for (int j = 0; j < q; ++j) {
+      if (!(L.sg[j] > cut)) continue;
+      sum = fma(L.V[a * q + j], L.W[b * q + j] / (L.sg[j] * L.sg[j]), sum);
+    }
+    if (tall) U[(int64_t)a * r + b] = sum;  // U is c x r = q x p
+    else U[(int64_t)b * r + a] = sum;       // U(b, a): c = p rows, r = q columns
+  }
+}
+
+template <typename T>
+static cur_status assemble_rect_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r, int c,
+                                     const int64_t* I, const int64_t* J, T* C, double* U, T* R) {
+  hipStream_t s = ctx->stream;
+  const int gc = (int)std::min<int64_t>((m * c + kThreads - 1) / kThreads, 8192);
+  hipLaunchKernelGGL((k_gather_C<T>), dim3(std::max(gc, 1)), dim3(kThreads), 0, s, A, m, lda, c, J, C);
+  const int gr = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 1024);
+  hipLaunchKernelGGL((k_gather_R<T>), dim3(std::max(gr, 1), r), dim3(kThreads), 0, s, A, n, lda, I, R);
+  hipLaunchKernelGGL((k_pinv_rect<T>), dim3(1), dim3(kThreads), 0, s, A, lda, r, c, I, J, U);
+  CUR_HIP_CHECK(hipGetLastError());
+  CUR_HIP_CHECK(hipStreamSynchronize(s));
+  return CUR_OK;
+}
+
+cur_status assemble_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                  int r, int c, const int64_t* I, const int64_t* J, void* C, double* U, void* R) {
+  if (dtype == CUR_F64)
+    return assemble_rect_impl<double>(ctx, (const double*)A, m, n, lda, r, c, I, J, (double*)C, U, (double*)R);
+  return assemble_rect_impl<float>(ctx, (const float*)A, m, n, lda, r, c, I, J, (float*)C, U, (float*)R);
+}
+
 cur_status assemble_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
                              int r, const int64_t* I, const int64_t* J, void* C, double* U, void* R) {
   if (dtype == CUR_F64)

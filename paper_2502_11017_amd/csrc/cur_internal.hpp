@@ -72,6 +72,7 @@ struct Node {
   double* lzv;       // kLz x r row-major: the factors v_s of those swaps
   const void* src;   // leaves: the matrix A this tree selects from (element T)
   int64_t lda;       // leaves: its leading dimension
+  int32_t trans;     // leaves: the tree selects from A^T (its rows are the columns of src)
   int64_t col0;      // leaves: first column of the block
   int64_t tclk[8];   // wall-clock ticks spent in controller steps (diagnostics):
                      // build, col phase, col fresh, col swaps, sort, whole ctl, LU, inverse
@@ -130,6 +131,7 @@ struct cur_ctx_s {
   int32_t* host_flag;   // pinned host word for polling
   int cu_count;
   int last_pinv;        // cur_assemble used the pseudo-inverse
+  int64_t* rect_discard;  // device, 256 entries: the index sets cur_select_rect does not return
   // measurement counters (cur_profile_*)
   int prof_on;
   unsigned long long* prof_bytes;   // device byte slots, one per timed launch
@@ -218,4 +220,18 @@ cur_status residual_noalloc_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A
 cur_status residual_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n,
                              int64_t lda, int r, const void* C, const double* U, const void* R,
                              int prec, double* cheb, double* fro_rel);
+
+// Rectangular cross, r rows and c columns (select.hip, greedy.hip,
+// assemble.hip, residual.hip).  `discard` (device, 2 max(r, c) entries)
+// receives the index sets of the two trees that are not returned.
+cur_status select_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                int r, int c, const cur_opts& o, int64_t* I, int64_t* J, int64_t* discard,
+                                cur_info* info);
+cur_status greedy_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                int r, int c, int64_t* I, int64_t* J, cur_info* info);
+cur_status assemble_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                  int r, int c, const int64_t* I, const int64_t* J, void* C, double* U, void* R);
+cur_status residual_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                  int r, int c, const void* C, const double* U, const void* R, double* cheb,
+                                  double* fro_rel);
 }  // namespace cur

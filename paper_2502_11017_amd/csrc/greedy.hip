@@ -153,14 +153,14 @@ __global__ __launch_bounds__(kThreads) void k_gr_update(double* __restrict__ W, 
 }
 
 template <typename T>
-static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r, int64_t* I,
-                              int64_t* J, cur_info* info, cur_trace* trace) {
+static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int rr, int rc,
+                              int64_t* I, int64_t* J, cur_info* info, cur_trace* trace) {
   cur_status st = ensure_groups(ctx);
   if (st != CUR_OK) return st;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t mn = (size_t)m * (size_t)n;
   const size_t need = 2 * al(sizeof(double) * mn) + al(sizeof(double) * m) + al(sizeof(double) * n) + al(m) + al(n) +
-                      2 * al(sizeof(GreedyState)) + 2 * al(sizeof(int64_t) * r);
+                      2 * al(sizeof(GreedyState)) + al(sizeof(int64_t) * rr) + al(sizeof(int64_t) * rc);
   st = ensure_arena(ctx, need);
   if (st != CUR_OK) return st;
   Arena ar{(char*)ctx->arena, ctx->arena_bytes, 0};
@@ -172,8 +172,8 @@ static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
   uint8_t* selc = (uint8_t*)ar.take(n);
   GreedyState* str = (GreedyState*)ar.take(sizeof(GreedyState));
   GreedyState* stc = (GreedyState*)ar.take(sizeof(GreedyState));
-  int64_t* ordr = (int64_t*)ar.take(sizeof(int64_t) * r);
-  int64_t* ordc = (int64_t*)ar.take(sizeof(int64_t) * r);
+  int64_t* ordr = (int64_t*)ar.take(sizeof(int64_t) * rr);
+  int64_t* ordc = (int64_t*)ar.take(sizeof(int64_t) * rc);
   if (!ordc) {
     set_error("workspace layout overflow");
     return CUR_ERR_INTERNAL;
@@ -202,61 +202,59 @@ static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
     hipLaunchKernelGGL((k_gr_load_cols<T>), dim3((unsigned)tbx, (unsigned)tby), dim3(kThreads), 0, sc, A, m, n, lda,
                        Wc);
   }
-  auto axis = [&](double* W, int64_t len, int64_t cnt, double* nrm, uint8_t* sel, GreedyState* gs, int64_t* ord,
-                  hipStream_t s) {
+  auto axis = [&](double* W, int64_t len, int64_t cnt, int steps, double* nrm, uint8_t* sel, GreedyState* gs,
+                  int64_t* ord, hipStream_t s) {
     const unsigned nb = (unsigned)((cnt + kThreads / 64 - 1) / (kThreads / 64));
     hipLaunchKernelGGL(k_gr_norms, dim3(nb), dim3(kThreads), 0, s, W, len, cnt, nrm);
-    for (int t = 0; t < r; ++t) {
+    for (int t = 0; t < steps; ++t) {
       hipLaunchKernelGGL(k_gr_argmax, dim3(1), dim3(kThreads), 0, s, nrm, sel, cnt, eps2, t, gs, ord);
-      if (t + 1 < r) hipLaunchKernelGGL(k_gr_update, dim3(nb), dim3(kThreads), 0, s, W, len, cnt, nrm, sel, gs);
+      if (t + 1 < steps) hipLaunchKernelGGL(k_gr_update, dim3(nb), dim3(kThreads), 0, s, W, len, cnt, nrm, sel, gs);
     }
   };
-  axis(Wr, n, m, nr, selr, str, ordr, sr);
-  axis(Wc, m, n, nc, selc, stc, ordc, sc);
+  axis(Wr, n, m, rr, nr, selr, str, ordr, sr);
+  axis(Wc, m, n, rc, nc, selc, stc, ordc, sc);
   CUR_HIP_CHECK(hipGetLastError());
   CUR_HIP_CHECK(hipEventRecord(ctx->gjoin[0], sr));
   CUR_HIP_CHECK(hipEventRecord(ctx->gjoin[1], sc));
   CUR_HIP_CHECK(hipStreamWaitEvent(s0, ctx->gjoin[0], 0));
   CUR_HIP_CHECK(hipStreamWaitEvent(s0, ctx->gjoin[1], 0));
   GreedyState hs[2];
-  std::vector<int64_t> hr(r, -1), hc(r, -1);
+  std::vector<int64_t> hr(rr, -1), hc(rc, -1);
   CUR_HIP_CHECK(hipMemcpyAsync(&hs[0], str, sizeof(GreedyState), hipMemcpyDeviceToHost, s0));
   CUR_HIP_CHECK(hipMemcpyAsync(&hs[1], stc, sizeof(GreedyState), hipMemcpyDeviceToHost, s0));
-  CUR_HIP_CHECK(hipMemcpyAsync(hr.data(), ordr, sizeof(int64_t) * r, hipMemcpyDeviceToHost, s0));
-  CUR_HIP_CHECK(hipMemcpyAsync(hc.data(), ordc, sizeof(int64_t) * r, hipMemcpyDeviceToHost, s0));
+  CUR_HIP_CHECK(hipMemcpyAsync(hr.data(), ordr, sizeof(int64_t) * rr, hipMemcpyDeviceToHost, s0));
+  CUR_HIP_CHECK(hipMemcpyAsync(hc.data(), ordc, sizeof(int64_t) * rc, hipMemcpyDeviceToHost, s0));
   CUR_HIP_CHECK(hipStreamSynchronize(s0));
   if (hs[0].nonfinite || hs[1].nonfinite) {
     set_error("A holds NaN or Inf");
     return CUR_ERR_NONFINITE;
   }
   const int qr = hs[0].count, qc = hs[1].count;
-  std::vector<int64_t> oI(r, -1), oJ(r, -1);
+  std::vector<int64_t> oI(rr, -1), oJ(rc, -1);
   for (int t = 0; t < qr; ++t) oI[t] = hr[t];
   for (int t = 0; t < qc; ++t) oJ[t] = hc[t];
   std::sort(oI.begin(), oI.begin() + qr);
   std::sort(oJ.begin(), oJ.begin() + qc);
-  CUR_HIP_CHECK(hipMemcpyAsync(I, oI.data(), sizeof(int64_t) * r, hipMemcpyHostToDevice, s0));
-  CUR_HIP_CHECK(hipMemcpyAsync(J, oJ.data(), sizeof(int64_t) * r, hipMemcpyHostToDevice, s0));
+  CUR_HIP_CHECK(hipMemcpyAsync(I, oI.data(), sizeof(int64_t) * rr, hipMemcpyHostToDevice, s0));
+  CUR_HIP_CHECK(hipMemcpyAsync(J, oJ.data(), sizeof(int64_t) * rc, hipMemcpyHostToDevice, s0));
   CUR_HIP_CHECK(hipStreamSynchronize(s0));
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->rank = std::min(qr, qc);
     info->logvol = std::nan("");
   }
-  if (trace) {  // one record: rows and columns in the order chosen
+  if (trace) {  // one record: rows and columns in the order chosen (square calls only)
     int64_t* mt = trace->meta;
     for (int f = 0; f < kMetaFields; ++f) mt[f] = 0;
     mt[2] = std::min(qr, qc);
-    mt[3] = (qr < r || qc < r) ? 1 : 0;
+    mt[3] = (qr < rr || qc < rc) ? 1 : 0;
     trace->vol_mant[0] = 0.0;
-    for (int t = 0; t < r; ++t) {
-      trace->I[t] = t < qr ? hr[t] : -1;
-      trace->J[t] = t < qc ? hc[t] : -1;
-    }
+    for (int t = 0; t < rr; ++t) trace->I[t] = t < qr ? hr[t] : -1;
+    for (int t = 0; t < rc; ++t) trace->J[t] = t < qc ? hc[t] : -1;
     trace->count = 1;
   }
-  if (qr < r || qc < r) {
-    set_error("fewer than r vectors above the rank threshold");
+  if (qr < rr || qc < rc) {
+    set_error("fewer vectors above the rank threshold than asked for");
     return CUR_ERR_RANK;
   }
   return CUR_OK;
@@ -264,8 +262,14 @@ static cur_status greedy_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int
 
 cur_status greedy_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda, int r,
                            int64_t* I, int64_t* J, cur_info* info, cur_trace* trace) {
-  if (dtype == CUR_F64) return greedy_impl<double>(ctx, (const double*)A, m, n, lda, r, I, J, info, trace);
-  return greedy_impl<float>(ctx, (const float*)A, m, n, lda, r, I, J, info, trace);
+  if (dtype == CUR_F64) return greedy_impl<double>(ctx, (const double*)A, m, n, lda, r, r, I, J, info, trace);
+  return greedy_impl<float>(ctx, (const float*)A, m, n, lda, r, r, I, J, info, trace);
+}
+
+cur_status greedy_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                int r, int c, int64_t* I, int64_t* J, cur_info* info) {
+  if (dtype == CUR_F64) return greedy_impl<double>(ctx, (const double*)A, m, n, lda, r, c, I, J, info, nullptr);
+  return greedy_impl<float>(ctx, (const float*)A, m, n, lda, r, c, I, J, info, nullptr);
 }
 
 }  // namespace cur

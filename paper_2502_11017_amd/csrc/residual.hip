@@ -132,12 +132,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
   }
 }
 
-// Bm = C U on FP64 MFMA, one 128-row x 128-column tile of Bm per block (r <= 128
-// columns, so one column tile), the same operand staging and lane layout as
-// k_resid_mfma with C as the row operand and U as the column operand.
+// Bm = C U on FP64 MFMA (C m x kd, U kd x r; kd = r for the square cross, c
+// for a rectangular one), one 128-row x 128-column tile of Bm per block
+// (r <= 128 columns, so one column tile), the same operand staging and lane
+// layout as k_resid_mfma with C as the row operand and U as the column
+// operand.
 template <typename T>
 __global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C, const double* __restrict__ U,
-                                                         int64_t m, int r, double* __restrict__ Bm) {
+                                                         int64_t m, int kd, int r, double* __restrict__ Bm) {
   __shared__ ResidLds L;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -148,14 +150,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < r; k0 += kKC) {
-    const int kc = min(kKC, r - k0);
+  for (int k0 = 0; k0 < kd; k0 += kKC) {
+    const int kc = min(kKC, kd - k0);
     {
       const int br = tid >> 1, bk = 16 * (tid & 1);
       const int64_t row = r0 + br;
       double vb[16], vr[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) vb[q] = (row < m && bk + q < kc) ? (double)C[row * r + k0 + bk + q] : 0.0;
+      for (int q = 0; q < 16; ++q) vb[q] = (row < m && bk + q < kc) ? (double)C[row * kd + k0 + bk + q] : 0.0;
       const int rk = tid >> 3, rc = 16 * (tid & 7);
 #pragma unroll
       for (int q = 0; q < 16; ++q) vr[q] = (rk < kc && rc + q < r) ? U[(int64_t)(k0 + rk) * r + rc + q] : 0.0;
@@ -239,7 +241,8 @@ static size_t residual_need(int64_t m, int64_t n, int r, int prec) {
 template <typename T>
 static cur_status residual_core(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r,
                                 const T* C, const double* U, const T* R, int prec, double* cheb,
-                                double* fro_rel, char* base) {
+                                double* fro_rel, char* base, int kd = 0) {
+  if (kd == 0) kd = r;  // columns of C: r, or c for a rectangular cross (native form only)
   hipStream_t s = ctx->stream;
   const bool mp = prec != CUR_PREC_NATIVE;  // FP32 input only (checked by the API)
   const int64_t gx = (n + kRT - 1) / kRT, gy = (m + kRT - 1) / kRT;
@@ -272,7 +275,7 @@ static cur_status residual_core(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
       set_error("matrix too tall for the residual grid");
       return CUR_ERR_ARG;
     }
-    hipLaunchKernelGGL((k_cu_mfma<T>), dim3((unsigned)gm), dim3(kThreads), 0, s, C, U, m, r, Bm);
+    hipLaunchKernelGGL((k_cu_mfma<T>), dim3((unsigned)gm), dim3(kThreads), 0, s, C, U, m, kd, r, Bm);
     hipLaunchKernelGGL((k_resid_mfma<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
                        lda, r, Bm, R, part);
   }
@@ -350,6 +353,19 @@ cur_status residual_noalloc_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A
                                  cheb, fro_rel, (char*)p);
   return residual_core<float>(ctx, (const float*)A, m, n, lda, r, (const float*)C, U, (const float*)R, prec, cheb,
                               fro_rel, (char*)p);
+}
+
+// The native residual of a rectangular cross: C m x c, U c x r, R r x n.
+cur_status residual_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                  int r, int c, const void* C, const double* U, const void* R, double* cheb,
+                                  double* fro_rel) {
+  cur_status st = ensure_arena(ctx, residual_need(m, n, r, CUR_PREC_NATIVE));
+  if (st != CUR_OK) return st;
+  if (dtype == CUR_F64)
+    return residual_core<double>(ctx, (const double*)A, m, n, lda, r, (const double*)C, U, (const double*)R,
+                                 CUR_PREC_NATIVE, cheb, fro_rel, (char*)ctx->arena, c);
+  return residual_core<float>(ctx, (const float*)A, m, n, lda, r, (const float*)C, U, (const float*)R,
+                              CUR_PREC_NATIVE, cheb, fro_rel, (char*)ctx->arena, c);
 }
 
 cur_status residual_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,

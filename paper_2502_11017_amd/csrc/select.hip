@@ -87,7 +87,9 @@ __global__ __launch_bounds__(kThreads) void k_amax(const ScanItem* __restrict__ 
 
 // ---------------------------------------------------------------- leaf set-up
 // panel(:, c) = A(:, c0 + c) for each leaf's block (the leaf's own matrix),
-// transposed through LDS.  grid (row tiles, column tiles of 64, leaves).
+// transposed through LDS.  grid (row tiles, column tiles of 64, leaves).  A
+// tree over A^T (trans) reads panel column c from row c0 + c of the source,
+// which is already contiguous (lanes along it).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes) {
   Node& nd = nodes[blockIdx.z];
@@ -99,6 +101,15 @@ __global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes) {
   __shared__ T tile[kTR][65];
   const T* A = (const T*)nd.src;
   const int64_t lda = nd.lda, c0 = nd.col0;
+  if (nd.trans) {
+    T* P = (T*)nd.panel;
+    for (int idx = threadIdx.x; idx < kTR * 64; idx += kThreads) {
+      const int cc = idx / kTR, rr = idx % kTR;
+      const int64_t i = r0 + rr;
+      if (i < m && cb + cc < nc) P[(int64_t)(cb + cc) * m + i] = A[(c0 + cb + cc) * lda + i];
+    }
+    return;
+  }
   // read kTR rows x 64 columns, lanes along the row
   for (int idx = threadIdx.x; idx < kTR * 64; idx += kThreads) {
     const int rr = idx >> 6, cc = idx & 63;
@@ -1378,6 +1389,7 @@ struct TreeJob {
   int64_t* I;
   int64_t* J;
   cur_info* info;
+  bool trans = false;       // select from A^T: m, n are A^T's shape, A and lda the source's
   cur_status status = CUR_OK;
   bool active = true;
   double theta = 0.0;
@@ -1406,7 +1418,9 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     std::vector<ScanItem> hitems(nj);
     int64_t maxm = 1;
     for (int j = 0; j < nj; ++j) {
-      hitems[j] = {jobs[j].A, jobs[j].m, jobs[j].n, jobs[j].lda};
+      // (a tree over A^T scans its source in the source's own shape)
+      hitems[j] = jobs[j].trans ? ScanItem{jobs[j].A, jobs[j].n, jobs[j].m, jobs[j].lda}
+                                : ScanItem{jobs[j].A, jobs[j].m, jobs[j].n, jobs[j].lda};
       maxm = std::max(maxm, jobs[j].m);
     }
     CUR_HIP_CHECK(hipMemsetAsync(d, 0, 16 * (size_t)nj, s));
@@ -1586,6 +1600,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
           nd.steps = (int)std::min<int64_t>(std::min<int64_t>(r, nd.nc), jb.m);
           nd.src = jb.A;
           nd.lda = jb.lda;
+          nd.trans = jb.trans ? 1 : 0;
           nd.col0 = c0;
         } else {
           const int pc = jb.count[l - 1], po = jb.off[l - 1];
@@ -1821,6 +1836,65 @@ cur_status select_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t 
   if (dtype == CUR_F64)
     return select_one<double>(ctx, (const double*)A, m, n, lda, r, o, I, J, info);
   return select_one<float>(ctx, (const float*)A, m, n, lda, r, o, I, J, info);
+}
+
+// Alg. 2 with a row count r and a column count c: J from the column-block
+// tree on A with rank c, I from the same tree on A^T with rank r (the row
+// blocks of A); each tree's other index set goes to `discard` (device,
+// max(r, c) entries per tree).  Trees of one rank bucket share one engine
+// run (their levels advance together), otherwise they run one after the
+// other.  Status: a rank shortfall of either, then a spent swap budget.
+template <typename T>
+static cur_status select_rect_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n, int64_t lda, int r, int c,
+                                   const cur_opts& o, int64_t* I, int64_t* J, int64_t* discard, cur_info* info) {
+  std::vector<TreeJob<T>> jobs(2);
+  cur_info inf[2];
+  for (int k = 0; k < 2; ++k) {
+    TreeJob<T>& jb = jobs[k];
+    const bool rows = k == 1;
+    jb.A = A;
+    jb.trans = rows;
+    jb.m = rows ? n : m;
+    jb.n = rows ? m : n;
+    jb.lda = lda;
+    jb.r = rows ? r : c;
+    jb.o = o;
+    jb.o.trace = nullptr;
+    jb.I = discard + (int64_t)k * std::max(r, c);
+    jb.J = rows ? I : J;
+    jb.info = &inf[k];
+  }
+  cur_status rc = CUR_OK;
+  if (rmax_bucket(r) == rmax_bucket(c)) {
+    rc = select_many<T>(ctx, rmax_bucket(r), jobs, nullptr);
+  } else {
+    for (int k = 0; k < 2 && rc == CUR_OK; ++k) {
+      std::vector<TreeJob<T>> one(1, jobs[k]);
+      rc = select_many<T>(ctx, rmax_bucket(one[0].r), one, nullptr);
+      jobs[k].status = one[0].status;
+    }
+  }
+  if (rc != CUR_OK) return rc;
+  if (info) {
+    *info = inf[0];
+    info->rank = std::min(inf[0].rank, inf[1].rank);
+    info->swaps += inf[1].swaps;
+    info->phases += inf[1].phases;
+    info->refreshes += inf[1].refreshes;
+    info->nodes += inf[1].nodes;
+    info->logvol = std::nan("");  // no single square cross
+  }
+  for (cur_status s : {CUR_ERR_RANK, CUR_WARN_NOCONV})
+    if (jobs[0].status == s || jobs[1].status == s) return s;
+  return jobs[0].status != CUR_OK ? jobs[0].status : jobs[1].status;
+}
+
+cur_status select_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,
+                                int r, int c, const cur_opts& o, int64_t* I, int64_t* J, int64_t* discard,
+                                cur_info* info) {
+  if (dtype == CUR_F64)
+    return select_rect_impl<double>(ctx, (const double*)A, m, n, lda, r, c, o, I, J, discard, info);
+  return select_rect_impl<float>(ctx, (const float*)A, m, n, lda, r, c, o, I, J, discard, info);
 }
 
 // Items of one dtype and one rank bucket run as one set of trees.

@@ -175,3 +175,29 @@ def test_noalloc_residual_limit_is_checked_on_host():
     assert L.cur_residual_noalloc(None, cur.F64, p, 4000, 64, 64, 16, p, p, p, 0, ctypes.byref(cheb),
                                   None) == cur.ERR_ARG
     assert "ctx" in cur.last_error()
+
+
+def test_rect_argument_errors_on_host():
+    """The rectangular entry points check their counts and options before any
+    device work."""
+    L = cur.lib()
+    p = ctypes.c_void_p(1)
+    info = cur.Info()
+    for r, c, msg in ((0, 3, "r and c"), (3, 0, "r and c"), (3, 301, "r and c"), (129, 129, "r, c > 128")):
+        assert L.cur_select_rect(None, cur.F64, p, 400, 300, 300, r, c, None, p, p, ctypes.byref(info)) == cur.ERR_ARG
+        assert msg in cur.last_error()
+    o = cur.make_opts()
+    o.propose, o.mlp = 1, ctypes.c_void_p(1)
+    assert L.cur_select_rect(None, cur.F64, p, 400, 300, 300, 8, 16, ctypes.byref(o), p, p, None) == cur.ERR_ARG
+    assert "learned proposal" in cur.last_error()
+    o = cur.make_opts(col_block=8)
+    assert L.cur_select_rect(None, cur.F64, p, 400, 300, 300, 8, 16, ctypes.byref(o), p, p, None) == cur.ERR_ARG
+    assert "col_block must be >= r" in cur.last_error()
+    assert L.cur_select_rect(None, cur.F64, p, 400, 300, 300, 8, 16, None, p, p, None) == cur.ERR_ARG
+    assert "ctx" in cur.last_error()
+    assert L.cur_assemble_rect(None, cur.F64, p, 400, 300, 300, 65, 70, p, p, p, p, p) == cur.ERR_ARG
+    assert "min(r, c) <= 64" in cur.last_error()
+    cheb = ctypes.c_double()
+    assert L.cur_residual_rect(None, cur.F64, p, 400, 300, 300, 8, 16, p, None, p, ctypes.byref(cheb), None) \
+        == cur.ERR_ARG
+    assert "non-NULL" in cur.last_error()
