@@ -2,6 +2,7 @@
 
     python -m paper_2502_11017_amd.profsum stats   STATS_CSV [--top N] [--match TEXT]
     python -m paper_2502_11017_amd.profsum levels  TRACE_CSV [--skip N]
+    python -m paper_2502_11017_amd.profsum durations TRACE_CSV
     python -m paper_2502_11017_amd.profsum mfma    COUNTER_CSV [--match TEXT] [--simds N] [--ghz F]
     python -m paper_2502_11017_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
            --copy-bytes N --source FILE [--workload TEXT] [--command TEXT ...]
@@ -131,6 +132,25 @@ def level_table(path, skip=0):
     return "\n".join(out)
 
 
+def duration_table(path, names=("k_pass", "k_fresh", "k_ctl")):
+    """Percentiles (p10, p50, p90, max; us) of the per-launch durations of
+    the named kernels in a --kernel-trace CSV."""
+    d = {k: [] for k in names}
+    for r in _rows(path):
+        for k in names:
+            if k + "<" in r["Kernel_Name"] or k + "(" in r["Kernel_Name"]:
+                d[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = []
+    for k in names:
+        v = sorted(d[k])
+        if not v:
+            continue
+        pct = lambda q: v[min(len(v) - 1, int(round(q * (len(v) - 1))))]  # noqa: E731
+        out.append(f"  {k:8s} {len(v):5d} launches: p10 {pct(0.1):6.1f}  p50 {pct(0.5):6.1f}  p90 {pct(0.9):6.1f}"
+                   f"  max {v[-1]:6.1f}")
+    return "\n".join(out)
+
+
 def mfma_table(path, match=None, simds=1024, ghz=2.4):
     """Per kernel: dispatches, average duration, MFMA flops per dispatch by
     type, the rate they give over the dispatch's own duration, and the MFMA
@@ -216,6 +236,8 @@ def main(argv=None):
     lv = sub.add_parser("levels")
     lv.add_argument("csv")
     lv.add_argument("--skip", type=int, default=0, help="selections to leave out at the start (warm-up)")
+    du = sub.add_parser("durations")
+    du.add_argument("csv")
     mf = sub.add_parser("mfma")
     mf.add_argument("csv")
     mf.add_argument("--match", default=None)
@@ -240,6 +262,9 @@ def main(argv=None):
         return 0
     if a.cmd == "levels":
         print(level_table(a.csv, a.skip))
+        return 0
+    if a.cmd == "durations":
+        print(duration_table(a.csv))
         return 0
     if a.cmd == "mfma":
         print(mfma_table(a.csv, a.match, a.simds, a.ghz))

@@ -86,3 +86,13 @@ def test_mfma_table_flops_and_busy_share(tmp_path):
     assert f[1] == "2" and f[2] == "1000.0" and f[3] == "1.024"  # 2e6 MOPS x 512 per dispatch
     assert f[-2] == "1.0"  # 1.024 GFLOP in 1 ms
     assert f[-1] == "0.500"  # 1.2288e9 busy cycles / (1e6 ns x 2.4 GHz x 1024 SIMDs)
+
+
+def test_duration_percentiles(tmp_path):
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = [["void cur::k_fresh<double, 64>(...)", 0, 1000 * (i + 1)] for i in range(11)]
+    p = tmp_path / "t.csv"
+    _write(p, hdr, rows)
+    line = profsum.duration_table(str(p)).split()
+    assert line[:3] == ["k_fresh", "11", "launches:"]
+    assert line[4] == "2.0" and line[6] == "6.0" and line[8] == "10.0" and line[10] == "11.0"
