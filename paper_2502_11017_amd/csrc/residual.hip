@@ -14,16 +14,24 @@ namespace cur {
 
 // One 128 x 128 tile of E per block on FP64 MFMA (v_mfma_f64_16x16x4f64).
 // Wavefront w computes the 64 x 64 quadrant (w >> 1, w & 1) as 4 x 4 blocks of
-// 16 x 16.  Operand lanes: lane l supplies Bm[row 16i + (l & 15)][k + (l >> 4)]
-// and R[k + (l >> 4)][col 16j + (l & 15)]; the accumulator holds
-// D[4v + (l >> 4)][l & 15] in element v.  Out-of-range rows, columns and k are
-// zero operands, so they contribute E = 0.
-// The block's rows of Bm and columns of R are staged in LDS, KC values of k at
-// a time (rows padded by one double, so that the fragment reads are free of
-// bank conflicts); the fragments then come from LDS.  The LDS footprint
-// (~67 KB) and register count allow two blocks per CU, so one block's MFMAs
-// cover the other's staging and its reads of A in the epilogue.
-// part[3*block] = {max|E|, sum E^2, sum A^2} of the tile.
+// 16 x 16 (row group i, column group j).  Operand lanes: lane l supplies
+// Bm[row 16i + (l & 15)][k + (l >> 4)] and R[k + (l >> 4)][col 16j + (l & 15)];
+// the accumulator holds D[4v + (l >> 4)][l & 15] in element v.
+// The block's rows of Bm and columns of R are staged in LDS, kKC values of k at
+// a time, with coalesced loads (consecutive lanes read consecutive elements of
+// a row; rows padded by one double, so that the fragment reads are free of
+// bank conflicts).  k indices past the chunk are clamped to its last one when
+// loading and the staged entries [kc, kc rounded up to 4) are zeroed, so the
+// last MFMA step of a ragged chunk adds zeros.  The epilogue requests the A
+// values of row group i + 1 before reducing group i.
+// EDGE = false is the instance for tiles that lie wholly inside the matrix: no
+// load carries a bounds test, which lets all of them issue back to back (a
+// guarded load compiles to a branch with a wait for its data).  EDGE = true
+// guards rows and columns (out-of-range entries are zero operands and zero A,
+// so they contribute E = 0) and runs only over the ragged right and bottom
+// strips.  Tile (tx0 + blockIdx.x, ty0 + blockIdx.y) writes
+// part[3 (ty gx + tx)] = {max|E|, sum E^2, sum A^2} of the tile.
+// The LDS footprint (~67 KB) allows two blocks per CU.
 constexpr int kRT = 128, kKC = 32;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -33,44 +41,60 @@ struct ResidLds {
   double red[3][kThreads / 64];
 };
 
-template <typename T>
+template <typename T, bool EDGE>
 __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict__ A, int64_t m, int64_t n,
                                                          int64_t lda, int r, const double* __restrict__ Bm,
-                                                         const T* __restrict__ R, double* part) {
+                                                         const T* __restrict__ R, double* part, int tx0, int ty0,
+                                                         int gxall) {
   __shared__ ResidLds L;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.y * kRT, c0 = (int64_t)blockIdx.x * kRT;
+  const int tx = tx0 + blockIdx.x, ty = ty0 + blockIdx.y;
+  const int64_t r0 = (int64_t)ty * kRT, c0 = (int64_t)tx * kRT;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;  // quadrant inside the block
   f64x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // staging: element q of thread t is Bm[r0 + 8 q + (t >> 5)][k0 + (t & 31)] and
+  // R[k0 + 2 q + (t >> 7)][c0 + (t & 127)]
+  const int64_t brow = r0 + (tid >> 5), rcol = c0 + (tid & 127);
+  const double* bp = Bm + brow * r;
+  const T* rp = R + rcol;
   for (int k0 = 0; k0 < r; k0 += kKC) {
     const int kc = min(kKC, r - k0);
-    // stage: thread t loads Bm[r0 + (t >> 1)][k0 + 16 (t & 1) + q] and
-    // R[k0 + (t >> 3)][c0 + 16 (t & 7) + q], q < 16, all loads first
-    {
-      const int br = tid >> 1, bk = 16 * (tid & 1);
-      const int64_t row = r0 + br;
-      double vb[16], vr[16];
+    double vb[16];
+    T vr[16];
+    const int bk = k0 + min(tid & 31, kc - 1);
 #pragma unroll
-      for (int q = 0; q < 16; ++q)
-        vb[q] = (row < m && bk + q < kc) ? Bm[row * r + k0 + bk + q] : 0.0;
-      const int rk = tid >> 3, rc = 16 * (tid & 7);
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int64_t col = c0 + rc + q;
-        vr[q] = (rk < kc && col < n) ? (double)R[(int64_t)(k0 + rk) * n + col] : 0.0;
-      }
-      __syncthreads();  // the previous chunk's fragments have been read
-#pragma unroll
-      for (int q = 0; q < 16; ++q) L.B[br][bk + q] = vb[q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) L.R[rk][rc + q] = vr[q];
+    for (int q = 0; q < 16; ++q) {
+      if (EDGE) vb[q] = brow + 8 * q < m ? bp[(int64_t)8 * q * r + bk] : 0.0;
+      else vb[q] = bp[(int64_t)8 * q * r + bk];
     }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t off = (int64_t)(k0 + min(2 * q + (tid >> 7), kc - 1)) * n;
+      if (EDGE) vr[q] = rcol < n ? rp[off] : (T)0;
+      else vr[q] = rp[off];
+    }
+    __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll
+    for (int q = 0; q < 16; ++q) L.B[8 * q + (tid >> 5)][tid & 31] = vb[q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) L.R[2 * q + (tid >> 7)][tid & 127] = (double)vr[q];
     __syncthreads();
+    if (kc & 3) {  // ragged chunk: zero the staged k entries [kc, kc4)
+      const int kc4 = (kc + 3) & ~3;
+      for (int e = tid; e < kRT * 4; e += kThreads) {
+        const int kk = kc + (e & 3);
+        if (kk < kc4) {
+          L.B[e >> 2][kk] = 0.0;
+          L.R[kk][e >> 2] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
     for (int k = 0; k < kc; k += 4) {
       double af[4], bf[4];
 #pragma unroll
@@ -83,30 +107,41 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
-  double emax = 0.0, esq = 0.0, asq = 0.0;
+  // epilogue: A rows r0 + wr + 16 i + 4 v + lk, columns c0 + wc + 16 j + lr
+  const int64_t arow = r0 + wr + lk, acol = c0 + wc + lr;
+  const T* ap = A + arow * lda + acol;
+  auto load_a = [&](int i, T (&dst)[4][4]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double pa[4][4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = r0 + wr + 16 * i + 4 * v + lk;
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t col = c0 + wc + 16 * j + lr;
-        pa[j][v] = (row < m && col < n) ? (double)A[row * lda + col] : 0.0;
+        const int64_t off = (int64_t)(16 * i + 4 * v) * lda + 16 * j;
+        if (EDGE) dst[j][v] = (arow + 16 * i + 4 * v < m && acol + 16 * j < n) ? ap[off] : (T)0;
+        else dst[j][v] = ap[off];
       }
-    }
+  };
+  double emax = 0.0, esq = 0.0, asq = 0.0;
+  auto reduce = [&](int i, const T (&src)[4][4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double av = pa[j][v];
+        const double av = (double)src[j][v];
         const double e = av - acc[i][j][v];
         emax = nan_max(emax, fabs(e));
         esq = fma(e, e, esq);
         asq = fma(av, av, asq);
       }
-  }
+  };
+  T pa0[4][4], pa1[4][4];
+  load_a(0, pa0);
+  reduce(0, pa0);
+  load_a(1, pa1);
+  load_a(2, pa0);
+  reduce(1, pa1);
+  load_a(3, pa1);
+  reduce(2, pa0);
+  reduce(3, pa1);
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
     emax = nan_max(emax, __shfl_xor(emax, s, 64));
@@ -125,7 +160,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
       esq += L.red[1][q];
       asq += L.red[2][q];
     }
-    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t bid = (int64_t)ty * gxall + tx;
     part[3 * bid + 0] = emax;
     part[3 * bid + 1] = esq;
     part[3 * bid + 2] = asq;
@@ -276,8 +311,18 @@ static cur_status residual_core(cur_ctx ctx, const T* A, int64_t m, int64_t n, i
       return CUR_ERR_ARG;
     }
     hipLaunchKernelGGL((k_cu_mfma<T>), dim3((unsigned)gm), dim3(kThreads), 0, s, C, U, m, kd, r, Bm);
-    hipLaunchKernelGGL((k_resid_mfma<T>), dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, A, m, n,
-                       lda, r, Bm, R, part);
+    // interior tiles without bounds tests, then the ragged right strip (corner
+    // included) and bottom strip with them
+    const int nf = (int)(n / kRT), mf = (int)(m / kRT);
+    if (nf > 0 && mf > 0)
+      hipLaunchKernelGGL((k_resid_mfma<T, false>), dim3((unsigned)nf, (unsigned)mf), dim3(kThreads), 0, s, A, m,
+                         n, lda, r, Bm, R, part, 0, 0, (int)gx);
+    if (n % kRT)
+      hipLaunchKernelGGL((k_resid_mfma<T, true>), dim3(1u, (unsigned)gy), dim3(kThreads), 0, s, A, m, n, lda, r,
+                         Bm, R, part, nf, 0, (int)gx);
+    if (m % kRT && nf > 0)
+      hipLaunchKernelGGL((k_resid_mfma<T, true>), dim3((unsigned)nf, 1u), dim3(kThreads), 0, s, A, m, n, lda, r,
+                         Bm, R, part, 0, mf, (int)gx);
   }
   const int64_t g = std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (nparts + kThreads - 1) / kThreads));
   const int64_t chunk = (nparts + g - 1) / g;

@@ -207,14 +207,24 @@ def test_assemble_pinv_branch(orc):
     np.testing.assert_allclose(U.cpu().numpy(), oU, rtol=0, atol=1e-10 * np.abs(oU).max())
 
 
-@pytest.mark.parametrize("m,n,r", [(1000, 700, 24), (3000, 257, 100)])
-def test_residual_ragged(orc, m, n, r):
+# The residual runs 128 x 128 tiles: interior tiles without bounds tests, the
+# ragged right and bottom strips with them, and k in chunks of 32 whose ragged
+# last chunk is padded with zeros to a multiple of 4.  The shapes cover: both
+# strips (1000 x 700), a thin right strip and a 4-wide last chunk (3000 x 257,
+# r = 100), interior tiles only with r % 4 != 0 (256 x 384, r = 37), one-row /
+# one-column strips with r = 7 (129 x 130), no interior tile at all (100 x 90),
+# and FP32 input through the same tiles.
+@pytest.mark.parametrize("m,n,r,dt", [(1000, 700, 24, torch.float64), (3000, 257, 100, torch.float64),
+                                      (256, 384, 37, torch.float64), (129, 130, 7, torch.float64),
+                                      (100, 90, 5, torch.float64), (640, 515, 33, torch.float32)])
+def test_residual_ragged(orc, m, n, r, dt):
     Ah = W.gaussian(m, r, 3) @ W.gaussian(r, n, 4) + 1e-3 * W.gaussian(m, n, 5)
-    A = torch.from_numpy(Ah).to(DEV)
+    A = torch.from_numpy(Ah).to(dt).to(DEV)
+    Ah = A.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(6)
     I = np.sort(rng.choice(m, r, replace=False))
     J = np.sort(rng.choice(n, r, replace=False))
-    say(f"case residual m={m} n={n} r={r}")
+    say(f"case residual m={m} n={n} r={r} {dt}")
     C, U, R = cur.assemble(A, torch.from_numpy(I).to(DEV), torch.from_numpy(J).to(DEV))
     cheb, fro = cur.residual(A, C, U, R)
     oC, oU, oR, _ = orc.assemble(Ah, I, J)
