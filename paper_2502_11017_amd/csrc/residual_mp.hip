@@ -29,6 +29,7 @@
 
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "cur_device.hpp"
 #include "cur_internal.hpp"
@@ -37,6 +38,9 @@ namespace cur {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Plain vector types for the 16-byte staging copies (a HIP uint4/float4 is a
+// struct, whose copies go through memory and put the stage in scratch).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMT = 128;  // tile of E per block (rows and columns)
 constexpr int kMK = 32;   // k values per staged chunk
@@ -178,35 +182,56 @@ template <int PREC>
 struct MpStage {
   static constexpr int PIECES = kMK * MpOps<PREC>::ES / 16;  // 16-byte pieces per strip
   static constexpr int PER = 2 * kMT * PIECES / kMpThreads;
-  uint4 v[PER];
+  u32x4 v[PER];
 };
 
-template <int PREC>
+// Strips at or past lim: MODE 0 loads zeros, MODE 1 assumes there are none (no
+// test at all), MODE 2 loads strip lim - 1 again.  A tested load compiles to a
+// branch with a wait for its data, so modes 1 and 2 keep all loads in flight.
+// The pieces are expanded by a parameter pack rather than a loop: a loop of
+// plain copies is turned into a memcpy, which puts the stage in scratch memory.
+template <int PREC, int MODE>
+__device__ __forceinline__ void mp_load_piece(MpStage<PREC>& st, int q, const uint8_t* t1, const uint8_t* t2,
+                                              int64_t g0, int64_t lim, int rp, int k0) {
+  constexpr int ES = MpOps<PREC>::ES, PIECES = MpStage<PREC>::PIECES;
+  const int idx = threadIdx.x + q * kMpThreads;
+  const int term = idx / (kMT * PIECES), rem = idx % (kMT * PIECES);
+  const int strip = rem / PIECES, piece = rem % PIECES;
+  const int64_t g = MODE == 2 ? min(g0 + strip, lim - 1) : g0 + strip;
+  const int kk = k0 + piece * (16 / ES);  // < rp: k0 < rp and both are multiples of kMK
+  const uint8_t* src = term ? t2 : t1;
+  if (MODE == 0) st.v[q] = g < lim ? *(const u32x4*)(src + (g * rp + kk) * ES) : u32x4{0u, 0u, 0u, 0u};
+  else st.v[q] = *(const u32x4*)(src + (g * rp + kk) * ES);
+}
+
+template <int PREC, int MODE, int... Q>
+__device__ __forceinline__ void mp_load_pieces(MpStage<PREC>& st, const uint8_t* t1, const uint8_t* t2, int64_t g0,
+                                               int64_t lim, int rp, int k0, std::integer_sequence<int, Q...>) {
+  (mp_load_piece<PREC, MODE>(st, Q, t1, t2, g0, lim, rp, k0), ...);
+}
+
+template <int PREC, int MODE = 0>
 __device__ __forceinline__ void mp_load(MpStage<PREC>& st, const uint8_t* t1, const uint8_t* t2, int64_t g0,
                                         int64_t lim, int rp, int k0) {
-  constexpr int ES = MpOps<PREC>::ES, PIECES = MpStage<PREC>::PIECES, PER = MpStage<PREC>::PER;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  mp_load_pieces<PREC, MODE>(st, t1, t2, g0, lim, rp, k0, std::make_integer_sequence<int, MpStage<PREC>::PER>());
+}
+
+template <int PREC, int... Q>
+__device__ __forceinline__ void mp_store_pieces(const MpStage<PREC>& st, uint8_t* d1, uint8_t* d2,
+                                                std::integer_sequence<int, Q...>) {
+  constexpr int ROWB = MpOps<PREC>::ROWB, PIECES = MpStage<PREC>::PIECES;
+  auto one = [&](int q) {
     const int idx = threadIdx.x + q * kMpThreads;
     const int term = idx / (kMT * PIECES), rem = idx % (kMT * PIECES);
     const int strip = rem / PIECES, piece = rem % PIECES;
-    const int64_t g = g0 + strip;
-    const int kk = k0 + piece * (16 / ES);
-    const uint8_t* src = term ? t2 : t1;
-    st.v[q] = (g < lim && kk < rp) ? *(const uint4*)(src + (g * rp + kk) * ES) : make_uint4(0, 0, 0, 0);
-  }
+    *(u32x4*)((term ? d2 : d1) + strip * ROWB + piece * 16) = st.v[q];
+  };
+  (one(Q), ...);
 }
 
 template <int PREC>
 __device__ __forceinline__ void mp_store(const MpStage<PREC>& st, uint8_t* d1, uint8_t* d2) {
-  constexpr int ROWB = MpOps<PREC>::ROWB, PIECES = MpStage<PREC>::PIECES, PER = MpStage<PREC>::PER;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int idx = threadIdx.x + q * kMpThreads;
-    const int term = idx / (kMT * PIECES), rem = idx % (kMT * PIECES);
-    const int strip = rem / PIECES, piece = rem % PIECES;
-    *(uint4*)((term ? d2 : d1) + strip * ROWB + piece * 16) = st.v[q];
-  }
+  mp_store_pieces<PREC>(st, d1, d2, std::make_integer_sequence<int, MpStage<PREC>::PER>());
 }
 
 // ---------------------------------------------------------------- Bm = C U
@@ -217,18 +242,23 @@ __device__ __forceinline__ void mp_store(const MpStage<PREC>& st, uint8_t* d1, u
 // columns [32 (w >> 1), +32) of the block as the transposed product (first
 // operand: U's column strips).  Output: Bm split in the row-operand form
 // (m x rp per term) and, for FP8, one scale per 16-row tile of Bm.
-template <int PREC>
+// FULL = true: the block's kMT rows lie inside C and r = rp, so C's loads and
+// Bm's row stores need no bounds test, and U's strips past r (columns of Bm
+// past rp, never stored) repeat strip r - 1 instead of being zeroed: a repeat
+// of a column that is already there leaves the FP8 tile maxima unchanged.
+// Block b0 + blockIdx.x covers rows from kMT (b0 + blockIdx.x).
+template <int PREC, bool FULL>
 __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restrict__ C, int64_t m, int r, int rp,
                                                            const void* __restrict__ u1v, const void* __restrict__ u2v,
                                                            const float* __restrict__ us, void* __restrict__ o1v,
-                                                           void* __restrict__ o2v, float* __restrict__ os) {
+                                                           void* __restrict__ o2v, float* __restrict__ os, int b0) {
   using L_t = MpLds<PREC>;
   constexpr int ROWB = MpOps<PREC>::ROWB;
   __shared__ L_t L;
   __shared__ float cs[kMT / kST];  // FP8: scales of the block's 16-row tiles of C
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t rb0 = (int64_t)blockIdx.x * kMT;
+  const int64_t rb0 = (int64_t)(b0 + blockIdx.x) * kMT;
   const int wi = (w & 1) * 64, wj = (w >> 1) * 32;  // rows of Bm, columns of Bm
   if constexpr (PREC == CUR_PREC_FP8) {
     // row tile w of C: contiguous 16 r floats (C is m x r, leading dimension r)
@@ -256,12 +286,21 @@ __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restri
   float cv[8];
   MpStage<PREC> us_st;
   auto load_c = [&](int k0) {
+    if (FULL) {  // two 16-byte loads (C's rows start 16-byte aligned: r = rp, a multiple of 32)
+      const f32x4 c0v = *(const f32x4*)(C + gi * r + k0 + ck), c1v = *(const f32x4*)(C + gi * r + k0 + ck + 4);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = k0 + ck + q;
-      cv[q] = (gi < m && k < r) ? C[gi * r + k] : 0.0f;
+      for (int q = 0; q < 4; ++q) {
+        cv[q] = c0v[q];
+        cv[4 + q] = c1v[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + ck + q;
+        cv[q] = (gi < m && k < r) ? C[gi * r + k] : 0.0f;
+      }
     }
-    mp_load<PREC>(us_st, (const uint8_t*)u1v, (const uint8_t*)u2v, 0, r, rp, k0);  // U's r column strips
+    mp_load<PREC, FULL ? 2 : 0>(us_st, (const uint8_t*)u1v, (const uint8_t*)u2v, 0, r, rp, k0);  // U's r column strips
   };
   load_c(0);
   for (int k0 = 0; k0 < rp; k0 += kMK) {
@@ -313,7 +352,7 @@ __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restri
 #pragma unroll
     for (int b = 0; b < kNB; ++b) {
       const int64_t gi2 = rb0 + wi + 16 * b + lr;
-      if (gi2 >= m) continue;
+      if (!FULL && gi2 >= m) continue;
 #pragma unroll
       for (int a = 0; a < kNA; ++a) {
         const int j = wj + 16 * a + 4 * lk;
@@ -354,7 +393,7 @@ __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restri
       const float inv = 1.0f / sc;
       const int64_t gi2 = rb0 + wi + 16 * b + lr;
       if (w >> 1 == 0 && lane == 0 && rb0 + wi + 16 * b < m) os[(rb0 + wi + 16 * b) / kST] = sc;
-      if (gi2 >= m) continue;
+      if (!FULL && gi2 >= m) continue;
 #pragma unroll
       for (int a = 0; a < kNA; ++a) {
         const int j = wj + 16 * a + 4 * lk;
@@ -384,17 +423,23 @@ __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restri
 // loaded before the current chunk's products.  Operands staged in LDS kMK
 // values of k at a time (~41 KB BF16, ~25 KB FP8), two blocks per CU.
 // part[3*block] = {max|E|, sum E^2, sum A^2}.
-template <int PREC, bool VEC4>
+// EDGE = false is the instance for tiles wholly inside the matrix (operand
+// loads without bounds tests, no range checks in the epilogue); EDGE = true
+// runs over the ragged right and bottom strips.  Tile (tx0 + blockIdx.x,
+// ty0 + blockIdx.y) writes part[3 (ty gxall + tx)].
+template <int PREC, bool VEC4, bool EDGE>
 __global__ __launch_bounds__(kMpThreads, 2) __attribute__((amdgpu_waves_per_eu(4))) void k_resid_mp(const float* __restrict__ A, int64_t m, int64_t n,
                                                             int64_t lda, int rp, const void* __restrict__ a1v,
                                                             const void* __restrict__ a2v, const float* __restrict__ as,
                                                             const void* __restrict__ b1v, const void* __restrict__ b2v,
-                                                            const float* __restrict__ bs, double* part) {
+                                                            const float* __restrict__ bs, double* part, int tx0,
+                                                            int ty0, int gxall) {
   using L_t = MpLds<PREC>;
   __shared__ L_t L;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t rb0 = (int64_t)blockIdx.y * kMT, cb0 = (int64_t)blockIdx.x * kMT;
+  const int tx = tx0 + blockIdx.x, ty = ty0 + blockIdx.y;
+  const int64_t rb0 = (int64_t)ty * kMT, cb0 = (int64_t)tx * kMT;
   const int wi = (w & 1) * 64, wj = (w >> 1) * 32;  // rows, columns of the tile
   f32x4 acc[kNA][kNB], acc2[kNA][kNB];
 #pragma unroll
@@ -428,16 +473,16 @@ __global__ __launch_bounds__(kMpThreads, 2) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
   for (int b = 0; b < PF; ++b) load_a(b);
   MpStage<PREC> sx, sy;  // the next chunk of both operands, loaded a chunk ahead
-  mp_load<PREC>(sx, (const uint8_t*)b1v, (const uint8_t*)b2v, cb0, n, rp, 0);
-  mp_load<PREC>(sy, (const uint8_t*)a1v, (const uint8_t*)a2v, rb0, m, rp, 0);
+  mp_load<PREC, EDGE ? 0 : 1>(sx, (const uint8_t*)b1v, (const uint8_t*)b2v, cb0, n, rp, 0);
+  mp_load<PREC, EDGE ? 0 : 1>(sy, (const uint8_t*)a1v, (const uint8_t*)a2v, rb0, m, rp, 0);
   for (int k0 = 0; k0 < rp; k0 += kMK) {
     __syncthreads();  // the previous chunk's fragments have been read
     mp_store<PREC>(sx, L.x[0], L.x[1]);
     mp_store<PREC>(sy, L.y[0], L.y[1]);
     __syncthreads();
     if (k0 + kMK < rp) {
-      mp_load<PREC>(sx, (const uint8_t*)b1v, (const uint8_t*)b2v, cb0, n, rp, k0 + kMK);
-      mp_load<PREC>(sy, (const uint8_t*)a1v, (const uint8_t*)a2v, rb0, m, rp, k0 + kMK);
+      mp_load<PREC, EDGE ? 0 : 1>(sx, (const uint8_t*)b1v, (const uint8_t*)b2v, cb0, n, rp, k0 + kMK);
+      mp_load<PREC, EDGE ? 0 : 1>(sy, (const uint8_t*)a1v, (const uint8_t*)a2v, rb0, m, rp, k0 + kMK);
     }
     mp_chunk<PREC>(L, min(kMK, rp - k0), wj, wi, lr, lk, acc, acc2);
   }
@@ -447,16 +492,16 @@ __global__ __launch_bounds__(kMpThreads, 2) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
   for (int b = 0; b < kNB; ++b) {
     const int64_t i = rb0 + wi + 16 * b + lr;
-    if (i >= m) continue;
+    if (EDGE && i >= m) continue;
 #pragma unroll
     for (int a = 0; a < kNA; ++a) {
-      if (cb0 + wj + 16 * a >= n) continue;
+      if (EDGE && cb0 + wj + 16 * a >= n) continue;
       const float sc = (PREC == CUR_PREC_FP8) ? as[(rb0 + wi + 16 * b) / kST] * bs[(cb0 + wj + 16 * a) / kST] : 1.0f;
       const float avs[4] = {av[a][b].x, av[a][b].y, av[a][b].z, av[a][b].w};
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t j = cb0 + wj + 16 * a + 4 * lk + v;
-        if (j >= n) continue;
+        if (EDGE && j >= n) continue;
         float p = acc[a][b][v];
         if constexpr (PREC == CUR_PREC_FP8) p = sc * (p + 0.0625f * acc2[a][b][v]);
         const double x = (double)avs[v];
@@ -485,7 +530,7 @@ __global__ __launch_bounds__(kMpThreads, 2) __attribute__((amdgpu_waves_per_eu(4
       esq += L.red[1][q];
       asq += L.red[2][q];
     }
-    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t bid = (int64_t)ty * gxall + tx;
     part[3 * bid + 0] = emax;
     part[3 * bid + 1] = esq;
     part[3 * bid + 2] = asq;
@@ -546,30 +591,50 @@ cur_status residual_mp_launch(cur_ctx ctx, const float* A, int64_t m, int64_t n,
   auto grid = [](int64_t work) { return (int)std::max<int64_t>(1, std::min<int64_t>((work + kThreads - 1) / kThreads, 65536)); };
   auto wgrid = [](int64_t tiles) { return (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 65536)); };
   const bool vec4 = lda % 4 == 0 && n % 4 == 0 && ((uintptr_t)A % 16) == 0;
+  // interior tiles without bounds tests, then the ragged right strip (corner
+  // included) and bottom strip with them
+  const int nf = (int)(n / kMT), mf = (int)(m / kMT);
   auto tile_kernel = [&](auto prec_c) {
     constexpr int P = decltype(prec_c)::value;
-    if (vec4)
-      hipLaunchKernelGGL((k_resid_mp<P, true>), dim3((unsigned)gx, (unsigned)gy), dim3(kMpThreads), 0, s, A, m, n, lda,
-                         rp, a1, a2, as, b1, b2, bs, part);
-    else
-      hipLaunchKernelGGL((k_resid_mp<P, false>), dim3((unsigned)gx, (unsigned)gy), dim3(kMpThreads), 0, s, A, m, n, lda,
-                         rp, a1, a2, as, b1, b2, bs, part);
+    auto launch = [&](auto vec_c) {
+      constexpr bool V = decltype(vec_c)::value;
+      if (nf > 0 && mf > 0)
+        hipLaunchKernelGGL((k_resid_mp<P, V, false>), dim3((unsigned)nf, (unsigned)mf), dim3(kMpThreads), 0, s, A, m,
+                           n, lda, rp, a1, a2, as, b1, b2, bs, part, 0, 0, (int)gx);
+      if (n % kMT)
+        hipLaunchKernelGGL((k_resid_mp<P, V, true>), dim3(1u, (unsigned)gy), dim3(kMpThreads), 0, s, A, m, n, lda, rp,
+                           a1, a2, as, b1, b2, bs, part, nf, 0, (int)gx);
+      if (m % kMT && nf > 0)
+        hipLaunchKernelGGL((k_resid_mp<P, V, true>), dim3((unsigned)nf, 1u), dim3(kMpThreads), 0, s, A, m, n, lda, rp,
+                           a1, a2, as, b1, b2, bs, part, 0, mf, (int)gx);
+    };
+    if (vec4) launch(std::true_type());
+    else launch(std::false_type());
+  };
+  // Bm = C U: full row blocks without bounds tests when r is a multiple of kMK
+  auto cu_kernel = [&](auto prec_c) {
+    constexpr int P = decltype(prec_c)::value;
+    const int full = r == rp ? mf : 0;
+    if (full > 0)
+      hipLaunchKernelGGL((k_cu_lowp<P, true>), dim3((unsigned)full), dim3(kMpThreads), 0, s, C, m, r, rp, u1, u2, us,
+                         a1, a2, as, 0);
+    if (gy > full)
+      hipLaunchKernelGGL((k_cu_lowp<P, false>), dim3((unsigned)(gy - full)), dim3(kMpThreads), 0, s, C, m, r, rp, u1,
+                         u2, us, a1, a2, as, full);
   };
   if (prec == CUR_PREC_BF16X3) {
     hipLaunchKernelGGL((k_split_cols_bf16<float>), dim3(grid(n * rp)), dim3(kThreads), 0, s, R, r, n, n, rp,
                        (__bf16*)b1, (__bf16*)b2);
     hipLaunchKernelGGL((k_split_cols_bf16<double>), dim3(grid((int64_t)rp * rp)), dim3(kThreads), 0, s, U, r,
                        (int64_t)r, (int64_t)r, rp, (__bf16*)u1, (__bf16*)u2);
-    hipLaunchKernelGGL((k_cu_lowp<CUR_PREC_BF16X3>), dim3((unsigned)gy), dim3(kMpThreads), 0, s, C, m, r, rp, u1, u2,
-                       us, a1, a2, as);
+    cu_kernel(std::integral_constant<int, CUR_PREC_BF16X3>());
     tile_kernel(std::integral_constant<int, CUR_PREC_BF16X3>());
   } else {
     hipLaunchKernelGGL((k_split_cols_fp8<float>), dim3(wgrid((n + kST - 1) / kST)), dim3(kThreads), 0, s, R, r, n, n,
                        rp, (uint8_t*)b1, (uint8_t*)b2, bs);
     hipLaunchKernelGGL((k_split_cols_fp8<double>), dim3(wgrid((rp + kST - 1) / kST)), dim3(kThreads), 0, s, U, r,
                        (int64_t)r, (int64_t)r, rp, (uint8_t*)u1, (uint8_t*)u2, us);
-    hipLaunchKernelGGL((k_cu_lowp<CUR_PREC_FP8>), dim3((unsigned)gy), dim3(kMpThreads), 0, s, C, m, r, rp, u1, u2, us,
-                       a1, a2, as);
+    cu_kernel(std::integral_constant<int, CUR_PREC_FP8>());
     tile_kernel(std::integral_constant<int, CUR_PREC_FP8>());
   }
   CUR_HIP_CHECK(hipGetLastError());

@@ -98,13 +98,16 @@ def test_reduced_precision_within_bound(c4_small, oracle_resid, prec, name):
     assert abs(fro - ofro) <= bound / rms_a
 
 
-@pytest.mark.parametrize("m,n,r,pad", [(1000, 515, 40, 0), (3001, 700, 100, 3), (513, 2049, 8, 1)])
+@pytest.mark.parametrize("m,n,r,pad", [(1000, 515, 40, 0), (3001, 700, 100, 3), (513, 2049, 8, 1),
+                                       (1000, 515, 64, 0), (640, 384, 32, 0)])
 @pytest.mark.parametrize("prec", [cur.PREC_BF16X3, cur.PREC_FP8])
 def test_reduced_precision_ragged(orc, m, n, r, pad, prec):
     """Ragged tiles (m, n not multiples of 128, r not a multiple of 32, r <= 64
     leaving half the column tiles of C U empty) and a leading dimension that is
     not a multiple of 4 (scalar loads of A instead of 16-byte ones), within
-    the same bounds against the oracle."""
+    the same bounds against the oracle.  r = 64 and r = 32 (multiples of 32)
+    take the untested row blocks of C U, whose strips of U past r repeat the
+    last one; 640 x 384 has interior tiles only."""
     Ah = W.gaussian(m, r, 70) @ W.gaussian(r, n, 71) / np.sqrt(r) + 1e-3 * W.gaussian(m, n, 72)
     full = torch.zeros((m, n + pad), dtype=torch.float32, device=DEV)
     full[:, :n] = torch.from_numpy(Ah).to(torch.float32).to(DEV)
