@@ -413,6 +413,20 @@ __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restri
 }
 
 // ---------------------------------------------------------------- the tile kernel
+// The chip hands workgroups to its 8 XCDs in turn (linear id mod 8), each XCD
+// with its own L2.  Taken in grid order, the few column tiles of a tall
+// matrix's row strip (consecutive ids) land on different XCDs and each of them
+// fetches the strip's row operand (at 2^20 x 1024, r = 128, BF16x3: 8.7 GB
+// fetched per call instead of 4.8).  xcd_tile maps linear id L of a grid of
+// `total` tiles to tile T such that XCD x takes one contiguous range of tiles,
+// in order: [x base + min(x, rem), ...) with base = total / 8, rem = total % 8
+// (a bijection on [0, total)).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t total) {
+  const int64_t x = L % kXcds, local = L / kXcds, base = total / kXcds, rem = total % kXcds;
+  return x * base + min(x, rem) + local;
+}
+
 // One 128 x 128 tile of E per block; wavefront w computes rows [64 (w & 1),
 // +64) x columns [32 (w >> 1), +32) as the transposed product P^T = R^T Bm^T
 // (first operand: R's column strips), so a lane's four results are four
@@ -425,8 +439,9 @@ __global__ __launch_bounds__(kMpThreads, 2) void k_cu_lowp(const float* __restri
 // part[3*block] = {max|E|, sum E^2, sum A^2}.
 // EDGE = false is the instance for tiles wholly inside the matrix (operand
 // loads without bounds tests, no range checks in the epilogue); EDGE = true
-// runs over the ragged right and bottom strips.  Tile (tx0 + blockIdx.x,
-// ty0 + blockIdx.y) writes part[3 (ty gxall + tx)].
+// runs over the ragged right and bottom strips.  Tiles are taken in the
+// XCD-contiguous order of xcd_tile; tile (tx0 + tile % gx, ty0 + tile / gx)
+// writes part[3 (ty gxall + tx)].
 template <int PREC, bool VEC4, bool EDGE>
 __global__ __launch_bounds__(kMpThreads, 2) __attribute__((amdgpu_waves_per_eu(4))) void k_resid_mp(const float* __restrict__ A, int64_t m, int64_t n,
                                                             int64_t lda, int rp, const void* __restrict__ a1v,
@@ -438,7 +453,8 @@ __global__ __launch_bounds__(kMpThreads, 2) __attribute__((amdgpu_waves_per_eu(4
   __shared__ L_t L;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int tx = tx0 + blockIdx.x, ty = ty0 + blockIdx.y;
+  const int64_t tile = xcd_tile((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
+  const int tx = tx0 + (int)(tile % gridDim.x), ty = ty0 + (int)(tile / gridDim.x);
   const int64_t rb0 = (int64_t)ty * kMT, cb0 = (int64_t)tx * kMT;
   const int wi = (w & 1) * 64, wj = (w >> 1) * 32;  // rows, columns of the tile
   f32x4 acc[kNA][kNB], acc2[kNA][kNB];
