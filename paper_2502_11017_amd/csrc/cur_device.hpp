@@ -24,6 +24,13 @@ struct Cand {
   int32_t pos;
 };
 
+// Global-address-space view of a device pointer: loads and stores through it
+// become global_* instructions, whose completion counts apart from LDS and
+// scalar loads, so a wait for one does not drain the other (a generic pointer
+// gives flat instructions, which count as both).
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T*;
+
 // Maximum that keeps a NaN: once either operand is NaN the result is NaN
 // (fmax would drop it), so a non-finite residual entry reaches the caller.
 __device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }

@@ -91,12 +91,6 @@ struct AcaBest {
   }
 };
 
-// Global-address-space view of a device pointer: the streaming kernels'
-// loads and stores become global_* instructions, whose completion counts
-// apart from LDS and scalar loads, so a wait for one does not drain the other.
-template <typename T>
-using GPtr = __attribute__((address_space(1))) T*;
-
 // Element at byte offset `off` of a column whose base is wavefront-uniform:
 // a scalar base plus one 32-bit offset register per lane, shared by every
 // load and store of the row (the selection checks m * sizeof(T) < 2^32).
@@ -433,8 +427,12 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   const int64_t row0 = (int64_t)tile * kTileRows;
   const int64_t row = row0 + tid;
   const bool valid = row < m;
-  double* W = (double*)nd.work;
-  const T* P = (const T*)nd.panel;
+  // global-address-space views: the A loads and B stores are global_*
+  // instructions, whose completion counts apart from LDS (generic pointers
+  // give flat ones, which also count as LDS operations, so each LDS read of an
+  // index would wait for the previous loads of A)
+  const GPtr<double> W = (GPtr<double>)nd.work;
+  const GPtr<const T> P = (GPtr<const T>)nd.panel;
 
   constexpr int CB = RMAX <= 64 ? RMAX : 16;  // columns of X staged per chunk
   constexpr int U = RMAX <= 64 ? 16 : 8;      // loads of A(row, Jp_k) in flight
@@ -452,13 +450,23 @@ __global__ __launch_bounds__(kThreads) void k_fresh(Node* nodes, unsigned long l
   __syncthreads();
   const int slot = sslot[tid];
   RowBest<double> rb;
+  // X chunk: all of a thread's entries are requested before the first is
+  // stored (clamped indices, no tests: entries k >= r are never read, and
+  // columns j >= nb only feed accumulators that are not stored)
+  constexpr int XPER = RMAX * CB / kThreads;
+  static_assert(RMAX * CB % kThreads == 0, "X staging");
+  const GPtr<const double> Xg = (GPtr<const double>)nd.X;
   for (int c0 = 0; c0 < r; c0 += CB) {
     const int nb = min(CB, r - c0);
-    __syncthreads();
-    for (int idx = tid; idx < r * CB; idx += kThreads) {
-      const int k = idx / CB, j = idx % CB;
-      sX[idx] = (j < nb) ? nd.X[(int64_t)k * r + c0 + j] : 0.0;
+    double xv[XPER];
+#pragma unroll
+    for (int q = 0; q < XPER; ++q) {
+      const int idx = tid + q * kThreads, k = idx / CB, j = idx % CB;
+      xv[q] = Xg[(int64_t)min(k, r - 1) * r + c0 + min(j, nb - 1)];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < XPER; ++q) sX[tid + q * kThreads] = xv[q];
     __syncthreads();
     if (valid) {
       double acc[CB];

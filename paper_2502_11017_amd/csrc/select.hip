@@ -621,12 +621,22 @@ __device__ void ctl_col_phase_reg(Node& nd, CtlLds<T, RMAX>& L, double lim) {
   auto fresh = [&]() {
     const int64_t tf = wall_clock64();
     {
+      // Every load is issued unconditionally from a valid address (column and
+      // k clamped into range; entries for k >= r are not stored), so all 32
+      // are in flight together: a tested load compiles to a branch with a
+      // wait for its data.  Columns c >= nc are zeroed by a mask the optimiser
+      // cannot turn back into a branch.
       const int c = tid & 127;
+      const GPtr<const T> Pc = (GPtr<const T>)P + (int64_t)min(c, nc - 1) * m;
+      uint32_t cmask = c < nc ? 0xffffffffu : 0u;
+      asm("" : "+v"(cmask));
       double v[32];
 #pragma unroll
       for (int q = 0; q < 32; ++q) {
         const int k = (tid >> 7) + 2 * q;
-        v[q] = (c < nc && k < r) ? (double)P[(int64_t)c * m + L.sI[k]] : 0.0;
+        const double x = (double)Pc[L.sI[min(k, r - 1)]];
+        const uint64_t bits = (uint64_t)__double_as_longlong(x) & (((uint64_t)cmask << 32) | cmask);
+        v[q] = __longlong_as_double((long long)bits);
       }
 #pragma unroll
       for (int q = 0; q < 32; ++q) {
