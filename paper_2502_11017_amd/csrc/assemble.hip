@@ -64,7 +64,9 @@ __global__ __launch_bounds__(kThreads) void k_assemble_U(const T* __restrict__ A
   const double* diag;
   int dstride;
   if constexpr (RMAX <= 64) {
-    ok = lu_fwd_reg<RMAX>([&](int p, int c) { return (double)A[I[p] * lda + J[c]]; }, r, R, L.B, L.lu);
+    const GPtr<const T> Ag = (GPtr<const T>)A;
+    const GPtr<const int64_t> Ig = (GPtr<const int64_t>)I, Jg = (GPtr<const int64_t>)J;
+    ok = lu_fwd_reg<RMAX>([&](int p, int c) { return (double)Ag[Ig[p] * lda + Jg[c]]; }, r, R, L.B, L.lu);
     diag = L.lu.diag;
     dstride = 1;
   } else {

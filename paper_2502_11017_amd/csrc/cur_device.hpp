@@ -324,7 +324,9 @@ __device__ __forceinline__ double reg_pick(const double (&a)[NJ], int j) {
   return t[0];
 }
 
-// Factorization and forward substitution.  ldg(p, c) returns G(p, c).  U is
+// Factorization and forward substitution.  ldg(p, c) returns G(p, c) (called
+// with p, c < r only; a loader through global-address-space pointers keeps
+// the loads apart from the LDS wait counts).  U is
 // left in R.g and, column-major (element (p, c) at c * RMAX + p, physical
 // rows; entries left of a row's pivot are scratch), in LUl; S.diag / S.perm
 // hold U(k,k) and the row order.  Returns false (uniformly) on a zero pivot.
@@ -336,10 +338,21 @@ __device__ __forceinline__ bool lu_fwd_reg(LoadG ldg, int r, LuRegs<RMAX>& R, do
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool live = lane < r;
+  // G's entries: every load is issued unconditionally from a valid address
+  // (row and column clamped into range), lanes past r are zeroed by a mask
+  // the optimiser cannot turn back into a branch (a lane-divergent tested
+  // load compiles to a branch with a wait for its data), columns past r by
+  // a wavefront-uniform select.
+  uint32_t lmask = live ? 0xffffffffu : 0u;
+  asm("" : "+v"(lmask));
+  const uint64_t lm64 = ((uint64_t)lmask << 32) | lmask;
+  const int pl = min(lane, r - 1);
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int c = lu_col(w, j);
-    R.g[j] = (live && c < r) ? ldg(lane, c) : 0.0;
+    const double x = ldg(pl, min(c, r - 1));
+    const double xm = __longlong_as_double((long long)((uint64_t)__double_as_longlong(x) & lm64));
+    R.g[j] = c < r ? xm : 0.0;
     R.y[j] = (lane == c) ? 1.0 : 0.0;
   }
   R.pos = lane;

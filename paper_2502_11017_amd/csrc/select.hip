@@ -354,8 +354,9 @@ __device__ bool ctl_build_impl(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool w
   if constexpr (RMAX <= 64) {
     const int64_t tg = wall_clock64();
     LuRegs<RMAX> R;
+    const GPtr<const T> Pg = (GPtr<const T>)P;
     const bool okg = lu_fwd_reg<RMAX>(
-        [&](int p, int c) { return (double)P[(int64_t)L.sJp[c] * m + L.sI[p]]; }, r, R, L.B, L.lu);
+        [&](int p, int c) { return (double)Pg[(int64_t)L.sJp[c] * m + L.sI[p]]; }, r, R, L.B, L.lu);
     if (threadIdx.x == 0) nd.tclk[6] += wall_clock64() - tg;
     if (!okg) return false;
     if (want_vol && threadIdx.x == 0) lu_volume(L.lu.diag, 1, r, &L.s.vol_m, &L.s.vol_e);
