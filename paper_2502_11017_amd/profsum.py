@@ -4,6 +4,7 @@
     python -m paper_2502_11017_amd.profsum levels  TRACE_CSV [--skip N]
     python -m paper_2502_11017_amd.profsum durations TRACE_CSV
     python -m paper_2502_11017_amd.profsum mfma    COUNTER_CSV [--match TEXT] [--simds N] [--ghz F]
+    python -m paper_2502_11017_amd.profsum lds     COUNTER_CSV [--match TEXT] [--cus N] [--ghz F]
     python -m paper_2502_11017_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
            --copy-bytes N --source FILE [--workload TEXT] [--command TEXT ...]
            [--last N] [--bench-line FILE]
@@ -24,6 +25,13 @@ GRBM_GUI_ACTIVE) and prints per kernel the counted MFMA flops per dispatch
 (MOPS x 512), the rate over each dispatch's own duration, and the MFMA busy
 share: busy cycles summed over the SIMDs divided by (duration x clock x
 SIMDs), with the 2.4 GHz peak engine clock unless --ghz says otherwise.
+
+``lds`` reads one ``--pmc`` run of SQ_INSTS_LDS_LOAD_BANDWIDTH,
+SQ_LDS_IDX_ACTIVE and SQ_LDS_BANK_CONFLICT and prints per kernel the bytes
+read from LDS per dispatch (64-byte units x 64), their rate over the
+dispatch's duration and its share of the LDS peak (128 bytes per clock per
+compute unit), and the bank-conflict share of the cycles the LDS was busy
+with indexed accesses.
 
 ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into
 HBM bytes per launch of one kernel and prints them as JSON.  Both counters
@@ -186,6 +194,37 @@ def mfma_table(path, match=None, simds=1024, ghz=2.4):
     return "\n".join(out)
 
 
+def lds_table(path, match=None, cus=256, ghz=2.4):
+    """Per kernel: dispatches, average duration, bytes loaded from LDS per
+    dispatch, their rate and share of the LDS peak (128 B per clock per CU),
+    and bank-conflict cycles / indexed-access cycles."""
+    per = {}
+    for r in _rows(path):
+        if match and match not in r["Kernel_Name"]:
+            continue
+        d = int(r["Dispatch_Id"])
+        name, dur, cnt = per.setdefault(d, (r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), {}))
+        cnt[r["Counter_Name"]] = cnt.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    agg = {}
+    for name, dur, cnt in per.values():
+        a = agg.setdefault(name, dict(n=0, dur=0.0, ld=0.0, act=0.0, conf=0.0))
+        a["n"] += 1
+        a["dur"] += dur
+        a["ld"] += 64.0 * cnt.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0)
+        a["act"] += cnt.get("SQ_LDS_IDX_ACTIVE", 0.0)
+        a["conf"] += cnt.get("SQ_LDS_BANK_CONFLICT", 0.0)
+    peak = 128.0 * cus * ghz  # bytes per ns
+    out = [f"{'kernel':<52} {'disp':>4} {'avg us':>9} {'LDS GB':>8} {'TB/s':>6} {'of peak':>8} {'conflict':>9}"]
+    for name, a in sorted(agg.items(), key=lambda kv: -kv[1]["ld"]):
+        n = a["n"]
+        short = name if len(name) <= 52 else name[:49] + "..."
+        rate = a["ld"] / a["dur"] if a["dur"] > 0 else float("nan")  # bytes per ns = GB/s
+        conf = a["conf"] / a["act"] if a["act"] > 0 else float("nan")
+        out.append(f"{short:<52} {n:>4} {a['dur'] / n / 1e3:>9.1f} {a['ld'] / n / 1e9:>8.2f} {rate / 1e3:>6.1f} "
+                   f"{rate / peak:>8.3f} {conf:>9.3f}")
+    return "\n".join(out)
+
+
 def _per_dispatch(path):
     """{dispatch id: (kernel name, counter sum)}; a counter is summed over its
     instances (one row per XCD or channel)."""
@@ -243,6 +282,11 @@ def main(argv=None):
     mf.add_argument("--match", default=None)
     mf.add_argument("--simds", type=int, default=1024, help="SIMDs of the GPU (4 per compute unit)")
     mf.add_argument("--ghz", type=float, default=2.4, help="engine clock for the busy share")
+    ld = sub.add_parser("lds")
+    ld.add_argument("csv")
+    ld.add_argument("--match", default=None)
+    ld.add_argument("--cus", type=int, default=256, help="compute units of the GPU")
+    ld.add_argument("--ghz", type=float, default=2.4, help="engine clock for the LDS peak")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -265,6 +309,9 @@ def main(argv=None):
         return 0
     if a.cmd == "durations":
         print(duration_table(a.csv))
+        return 0
+    if a.cmd == "lds":
+        print(lds_table(a.csv, a.match, a.cus, a.ghz))
         return 0
     if a.cmd == "mfma":
         print(mfma_table(a.csv, a.match, a.simds, a.ghz))

@@ -96,3 +96,19 @@ def test_duration_percentiles(tmp_path):
     line = profsum.duration_table(str(p)).split()
     assert line[:3] == ["k_fresh", "11", "launches:"]
     assert line[4] == "2.0" and line[6] == "6.0" and line[8] == "10.0" and line[10] == "11.0"
+
+
+def test_lds_table_bytes_rate_and_conflict_share(tmp_path):
+    p = tmp_path / "l.csv"
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for d in (1, 2):  # two dispatches of 1 ms each, counters split over two instances
+        t0 = 10_000_000 * d
+        for ctr, v in (("SQ_INSTS_LDS_LOAD_BANDWIDTH", 1e8), ("SQ_LDS_IDX_ACTIVE", 4e6), ("SQ_LDS_BANK_CONFLICT", 1e6)):
+            rows += [[d, "k_resid_mp<1>", ctr, v / 2, t0, t0 + 1_000_000]] * 2
+    _write(p, hdr, rows)
+    f = profsum.lds_table(str(p), cus=256, ghz=2.4).splitlines()[1].split()
+    # 1e8 x 64 B = 6.4 GB per dispatch in 1 ms: 6.4 TB/s of 78.6 (128 B x 256 CUs x 2.4 GHz)
+    assert f[-5] == "1000.0" and f[-4] == "6.40" and f[-3] == "6.4"
+    assert abs(float(f[-2]) - 6.4e3 / (128 * 256 * 2.4)) < 1e-3
+    assert f[-1] == "0.250"
