@@ -164,48 +164,63 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
   }
   const Node& L = prev[nd.child0];
   const Node& R = prev[nd.child1];
-  __shared__ int s_st, nc_sh;
+  // The merged list is the sorted union of two ascending lists of original
+  // column indices (the children's J, at most 128 each).  Each entry's place
+  // is its rank in its own list plus the number of entries of the other list
+  // placed before it, the serial merge's rule (equal indices: the right
+  // child's first), counted over copies staged in LDS by all threads at once.
+  __shared__ int64_t sjl[128], sjr[128];
+  __shared__ int s_src;
+  const int qL = L.q, qR = R.q;
+  for (int a = tid; a < qL; a += blockDim.x) sjl[a] = L.Jc[L.Jp[a]];
+  for (int b = tid; b < qR; b += blockDim.x) sjr[b] = R.Jc[R.Jp[b]];
   if (tid == 0) {
-    const int qL = L.q, qR = R.q;
-    // sorted merge of two ascending lists of original column indices
-    int a = 0, b = 0, c = 0;
-    while (a < qL || b < qR) {
-      const int64_t ja = a < qL ? L.Jc[L.Jp[a]] : INT64_MAX;
-      const int64_t jb = b < qR ? R.Jc[R.Jp[b]] : INT64_MAX;
-      if (ja < jb) {
-        nd.Jc[c] = ja;
-        nd.srcpos[c] = (0 << 24) | L.Jp[a];
-        nd.colmap[c] = a;  // temporary: rank inside the left child's J
-        ++a;
-      } else {
-        nd.Jc[c] = jb;
-        nd.srcpos[c] = (1 << 24) | R.Jp[b];
-        nd.colmap[c] = (1 << 24) | b;
-        ++b;
-      }
-      ++c;
+    // the starting cross: from the child of larger volume (exact tie: left),
+    // or an ACA start (src = -1) when both children are rank-short
+    int src = -1;
+    if (!L.is_short && !R.is_short) {
+      const bool rg = (R.vol_e != L.vol_e) ? (R.vol_e > L.vol_e) : (R.vol_m > L.vol_m);
+      src = rg ? 1 : 0;
+    } else if (!L.is_short || !R.is_short) {
+      src = L.is_short ? 1 : 0;
     }
+    s_src = src;
+  }
+  __syncthreads();
+  const int src = s_src;
+  for (int a = tid; a < qL; a += blockDim.x) {
+    const int64_t ja = sjl[a];
+    int before = 0;
+    for (int b = 0; b < qR; ++b) before += sjr[b] <= ja;
+    const int cc = a + before;
+    nd.Jc[cc] = ja;
+    nd.srcpos[cc] = (0 << 24) | L.Jp[a];
+    nd.colmap[cc] = src < 0 ? cc : a;
+    if (src == 0) nd.Jp[a] = cc;
+  }
+  for (int b = tid; b < qR; b += blockDim.x) {
+    const int64_t jb = sjr[b];
+    int before = 0;
+    for (int a = 0; a < qL; ++a) before += sjl[a] < jb;
+    const int cc = b + before;
+    nd.Jc[cc] = jb;
+    nd.srcpos[cc] = (1 << 24) | R.Jp[b];
+    nd.colmap[cc] = src < 0 ? cc : ((1 << 24) | b);
+    if (src == 1) nd.Jp[b] = cc;
+  }
+  if (src >= 0) {
+    const Node& S = src ? R : L;
+    for (int k = tid; k < r; k += blockDim.x) nd.I[k] = S.I[k];
+  }
+  if (tid == 0) {
+    const int c = qL + qR;
     nd.nc = c;
     nd.swaps = nd.phases = nd.refreshes = 0;
     nd.nocap = nd.err = 0;
     nd.phase = nd.phase_swaps = nd.since = 0;
     nd.vol_m = 0.0;
     nd.vol_e = 0;
-    if (!L.is_short || !R.is_short) {
-      int src = 0;
-      if (!L.is_short && !R.is_short) {
-        const bool rg = (R.vol_e != L.vol_e) ? (R.vol_e > L.vol_e) : (R.vol_m > L.vol_m);
-        src = rg ? 1 : 0;
-      } else {
-        src = L.is_short ? 1 : 0;
-      }
-      const Node& S = src ? R : L;
-      for (int k = 0; k < r; ++k) nd.I[k] = S.I[k];
-      // positions of the chosen child's columns in the merged list
-      for (int cc = 0; cc < c; ++cc) {
-        const int tag = nd.colmap[cc];
-        if ((tag >> 24) == src) nd.Jp[tag & 0xffffff] = cc;
-      }
+    if (src >= 0) {
       nd.is_short = 0;
       nd.q = r;
       nd.t = r;
@@ -224,12 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
         nd.st = ST_ACA;
       }
     }
-    s_st = nd.st;
-    nc_sh = nd.nc;
   }
-  __syncthreads();
-  if (s_st == ST_ACA)
-    for (int cc = tid; cc < nc_sh; cc += blockDim.x) nd.colmap[cc] = cc;
 }
 
 // parent panel column c = child panel column (srcpos), for all merge nodes
