@@ -136,14 +136,27 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_f64(const TA* __restrict__
   // B: k row t / (TM / V), columns V (t % (TM / V)) + q
   const int ar = tid / (kGK / V), ak = V * (tid % (kGK / V));
   const int bk = tid / (TM / V), bc = V * (tid % (TM / V));
+  // a chunk whose rows, columns and k values all lie inside the operands loads
+  // without bounds tests (a lane-divergent tested load compiles to a branch
+  // with a wait for its data, one memory latency per load); the others keep
+  // the tests (their zeros feed the row sums of squares)
+  const bool inner_mn = i0 + TM <= M && j0 + TM <= N;
   for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
     double va[V], vb[V];
+    if (inner_mn && k0 + kGK <= ke) {
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      const int64_t i = i0 + ar, k = k0 + ak + q;
-      va[q] = (i < M && k < ke) ? (double)a[i * sai + k * sak] : 0.0;
-      const int64_t kk = k0 + bk, j = j0 + bc + q;
-      vb[q] = (kk < ke && j < N) ? (double)b[kk * sbk + j * sbj] : 0.0;
+      for (int q = 0; q < V; ++q) {
+        va[q] = (double)a[(i0 + ar) * sai + (k0 + ak + q) * sak];
+        vb[q] = (double)b[(k0 + bk) * sbk + (j0 + bc + q) * sbj];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const int64_t i = i0 + ar, k = k0 + ak + q;
+        va[q] = (i < M && k < ke) ? (double)a[i * sai + k * sak] : 0.0;
+        const int64_t kk = k0 + bk, j = j0 + bc + q;
+        vb[q] = (kk < ke && j < N) ? (double)b[kk * sbk + j * sbj] : 0.0;
+      }
     }
     __syncthreads();
 #pragma unroll

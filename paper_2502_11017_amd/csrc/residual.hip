@@ -171,7 +171,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_resid_mfma(const T* __restrict_
 // for a rectangular one), one 128-row x 128-column tile of Bm per block
 // (r <= 128 columns, so one column tile), the same operand staging and lane
 // layout as k_resid_mfma with C as the row operand and U as the column
-// operand.
+// operand.  Loads take clamped indices and carry no bounds test: rows past m
+// and columns past r only feed outputs that are not stored, and the staged k
+// entries [kc, kc rounded up to 4) of a ragged chunk are zeroed.
 template <typename T>
 __global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C, const double* __restrict__ U,
                                                          int64_t m, int kd, int r, double* __restrict__ Bm) {
@@ -185,24 +187,34 @@ __global__ __launch_bounds__(kThreads, 2) void k_cu_mfma(const T* __restrict__ C
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // staging: element q of thread t is C[r0 + 8 q + (t >> 5)][k0 + (t & 31)] and
+  // U[k0 + 2 q + (t >> 7)][t & 127]
+  const int ucol = min(tid & 127, r - 1);
   for (int k0 = 0; k0 < kd; k0 += kKC) {
     const int kc = min(kKC, kd - k0);
-    {
-      const int br = tid >> 1, bk = 16 * (tid & 1);
-      const int64_t row = r0 + br;
-      double vb[16], vr[16];
+    const int bk = k0 + min(tid & 31, kc - 1);
+    double vb[16], vr[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) vb[q] = (row < m && bk + q < kc) ? (double)C[row * kd + k0 + bk + q] : 0.0;
-      const int rk = tid >> 3, rc = 16 * (tid & 7);
+    for (int q = 0; q < 16; ++q) vb[q] = (double)C[min(r0 + 8 * q + (tid >> 5), m - 1) * kd + bk];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) vr[q] = (rk < kc && rc + q < r) ? U[(int64_t)(k0 + rk) * r + rc + q] : 0.0;
-      __syncthreads();
+    for (int q = 0; q < 16; ++q) vr[q] = U[(int64_t)(k0 + min(2 * q + (tid >> 7), kc - 1)) * r + ucol];
+    __syncthreads();  // the previous chunk's fragments have been read
 #pragma unroll
-      for (int q = 0; q < 16; ++q) L.B[br][bk + q] = vb[q];
+    for (int q = 0; q < 16; ++q) L.B[8 * q + (tid >> 5)][tid & 31] = vb[q];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) L.R[rk][rc + q] = vr[q];
-    }
+    for (int q = 0; q < 16; ++q) L.R[2 * q + (tid >> 7)][tid & 127] = vr[q];
     __syncthreads();
+    if (kc & 3) {  // ragged chunk: zero the staged k entries [kc, kc4)
+      const int kc4 = (kc + 3) & ~3;
+      for (int e = tid; e < kRT * 4; e += kThreads) {
+        const int kk = kc + (e & 3);
+        if (kk < kc4) {
+          L.B[e >> 2][kk] = 0.0;
+          L.R[kk][e >> 2] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
     for (int k = 0; k < kc; k += 4) {
       double af[4], bf[4];
 #pragma unroll
