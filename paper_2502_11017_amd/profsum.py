@@ -5,6 +5,7 @@
     python -m paper_2502_11017_amd.profsum durations TRACE_CSV
     python -m paper_2502_11017_amd.profsum mfma    COUNTER_CSV [--match TEXT] [--simds N] [--ghz F]
     python -m paper_2502_11017_amd.profsum lds     COUNTER_CSV [--match TEXT] [--cus N] [--ghz F]
+    python -m paper_2502_11017_amd.profsum waits   COUNTER_CSV [--match TEXT]
     python -m paper_2502_11017_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
            --copy-bytes N --source FILE [--workload TEXT] [--command TEXT ...]
            [--last N] [--bench-line FILE]
@@ -32,6 +33,11 @@ read from LDS per dispatch (64-byte units x 64), their rate over the
 dispatch's duration and its share of the LDS peak (128 bytes per clock per
 compute unit), and the bank-conflict share of the cycles the LDS was busy
 with indexed accesses.
+
+``waits`` reads one ``--pmc`` run of SQ_WAVE_CYCLES with SQ_WAIT_ANY,
+SQ_WAIT_INST_ANY and SQ_ACTIVE_INST_* counters and prints each as a share of
+the wave cycles: waiting on a wait count (memory, LDS), waiting for an
+instruction to issue (dependencies, a busy matrix pipe), and issuing.
 
 ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into
 HBM bytes per launch of one kernel and prints them as JSON.  Both counters
@@ -225,6 +231,27 @@ def lds_table(path, match=None, cus=256, ghz=2.4):
     return "\n".join(out)
 
 
+def waits_table(path, match=None):
+    """Per kernel: each SQ_WAIT_* / SQ_ACTIVE_INST_* counter of the run as a
+    share of SQ_WAVE_CYCLES (both in quad-cycles, summed over dispatches)."""
+    agg = {}
+    for r in _rows(path):
+        if match and match not in r["Kernel_Name"]:
+            continue
+        a = agg.setdefault(r["Kernel_Name"], {})
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    cols = ["SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+            "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_MISC"]
+    names = ["wait", "wait issue", "active", "VALU", "LDS", "VMEM", "misc"]
+    out = [f"{'kernel':<52} " + " ".join(f"{n:>10}" for n in names)]
+    for name, a in sorted(agg.items()):
+        wc = a.get("SQ_WAVE_CYCLES", 0.0)
+        short = name if len(name) <= 52 else name[:49] + "..."
+        vals = [a.get(c, float("nan")) / wc if wc > 0 else float("nan") for c in cols]
+        out.append(f"{short:<52} " + " ".join(f"{v:>10.3f}" for v in vals))
+    return "\n".join(out)
+
+
 def _per_dispatch(path):
     """{dispatch id: (kernel name, counter sum)}; a counter is summed over its
     instances (one row per XCD or channel)."""
@@ -287,6 +314,9 @@ def main(argv=None):
     ld.add_argument("--match", default=None)
     ld.add_argument("--cus", type=int, default=256, help="compute units of the GPU")
     ld.add_argument("--ghz", type=float, default=2.4, help="engine clock for the LDS peak")
+    wt = sub.add_parser("waits")
+    wt.add_argument("csv")
+    wt.add_argument("--match", default=None)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -309,6 +339,9 @@ def main(argv=None):
         return 0
     if a.cmd == "durations":
         print(duration_table(a.csv))
+        return 0
+    if a.cmd == "waits":
+        print(waits_table(a.csv, a.match))
         return 0
     if a.cmd == "lds":
         print(lds_table(a.csv, a.match, a.cus, a.ghz))

@@ -112,3 +112,16 @@ def test_lds_table_bytes_rate_and_conflict_share(tmp_path):
     assert f[-5] == "1000.0" and f[-4] == "6.40" and f[-3] == "6.4"
     assert abs(float(f[-2]) - 6.4e3 / (128 * 256 * 2.4)) < 1e-3
     assert f[-1] == "0.250"
+
+
+def test_waits_table_shares_of_wave_cycles(tmp_path):
+    p = tmp_path / "w.csv"
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for ctr, v in (("SQ_WAVE_CYCLES", 1000.0), ("SQ_WAIT_ANY", 400.0), ("SQ_WAIT_INST_ANY", 250.0),
+                   ("SQ_ACTIVE_INST_ANY", 200.0), ("SQ_ACTIVE_INST_VALU", 100.0)):
+        rows += [[1, "k_resid_mp<1>", ctr, v / 2, 0, 1000]] * 2  # two instances
+    _write(p, hdr, rows)
+    f = profsum.waits_table(str(p)).splitlines()[1].split()
+    assert f[-7:-3] == ["0.400", "0.250", "0.200", "0.100"]
+    assert f[-3] == "nan"  # a counter the run did not collect
