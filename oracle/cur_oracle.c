@@ -567,13 +567,30 @@ int oracle_tree_size(int64_t b) {
  * every level, level by level, index ascending.
  */
 static int select_impl(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
-                       int max_swaps, double theta_rel, int64_t* I_out, int64_t* J_out, orc_info* info,
-                       int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ);
+                       int max_swaps, double theta_rel, int polish, int64_t* I_out, int64_t* J_out,
+                       orc_info* info, int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ);
 
 int oracle_cur_select(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
                       int max_swaps, int64_t* I_out, int64_t* J_out, orc_info* info,
                       int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ) {
-  return select_impl(A, m, n, lda, r, w, tau, max_swaps, 0.0, I_out, J_out, info, tmeta, tvol, tI, tJ);
+  return select_impl(A, m, n, lda, r, w, tau, max_swaps, 0.0, 0, I_out, J_out, info, tmeta, tvol, tI, tJ);
+}
+
+/*
+ * The selection followed by a polish of the root's cross over the whole
+ * matrix: the same swap loop (row phase over all m rows, column phase over
+ * the candidate set) with every column 0..n-1 as a candidate, started from
+ * the root's (I, J).  When it ends without reaching the swap budget, the
+ * cross is dominant over the whole matrix: every entry of A(:,J) A(I,J)^-1
+ * and of A(I,J)^-1 A(I,:) is at most 1 + tau in magnitude, the maximal-volume
+ * condition of Sec. 1.1 on all of A rather than on the root's candidates.
+ * A rank-short root is returned as it is.  The trace, if given, holds one
+ * more record (the polish, at the level after the root, index 0).
+ */
+int oracle_cur_select_polish(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
+                             int max_swaps, int64_t* I_out, int64_t* J_out, orc_info* info,
+                             int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ) {
+  return select_impl(A, m, n, lda, r, w, tau, max_swaps, 0.0, 1, I_out, J_out, info, tmeta, tvol, tI, tJ);
 }
 
 /*
@@ -586,12 +603,13 @@ int oracle_cur_select(const double* A, int64_t m, int64_t n, int64_t lda, int r,
 int oracle_cur_select_theta(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
                             int max_swaps, double theta_rel, int64_t* I_out, int64_t* J_out, orc_info* info) {
   if (!(theta_rel > 0.0)) return ORC_ERR_ARG;
-  return select_impl(A, m, n, lda, r, w, tau, max_swaps, theta_rel, I_out, J_out, info, NULL, NULL, NULL, NULL);
+  return select_impl(A, m, n, lda, r, w, tau, max_swaps, theta_rel, 0, I_out, J_out, info, NULL, NULL, NULL,
+                     NULL);
 }
 
 static int select_impl(const double* A, int64_t m, int64_t n, int64_t lda, int r, int w, double tau,
-                       int max_swaps, double theta_rel, int64_t* I_out, int64_t* J_out, orc_info* info,
-                       int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ) {
+                       int max_swaps, double theta_rel, int polish, int64_t* I_out, int64_t* J_out,
+                       orc_info* info, int64_t* tmeta, double* tvol, int64_t* tI, int64_t* tJ) {
   if (info) memset(info, 0, sizeof(*info));
   if (!A || !I_out || !J_out || m < 1 || n < 1 || lda < n || r < 1 || (int64_t)r > m ||
       (int64_t)r > n || w < 0 || tau < 0.0 || max_swaps < 0)
@@ -669,6 +687,19 @@ static int select_impl(const double* A, int64_t m, int64_t n, int64_t lda, int r
     cnt = nxt;
   }
   node_t* root = &cur[0];
+  if (polish && status >= 0 && !root->is_short) {
+    /* the polish: the swap loop on all n columns, from the root's cross */
+    memset(&root->st, 0, sizeof(root->st));
+    swap_loop(A, m, lda, r, root->I, root->J, cols, (int)n, tau, max_swaps, &root->st);
+    nodes++;
+    phases += root->st.phases; refreshes += root->st.refreshes; swaps += root->st.swaps;
+    anynocap |= root->st.nocap;
+    if (root->st.err) status = root->st.err;
+    else if (node_volume(A, lda, r, root) != 0) status = ORC_ERR_INTERNAL;
+    root->promoted = 0;
+    ++level;
+    if (trace) record(root, level, 0, r, tmeta, tvol, tI, tJ, slot++);
+  }
   if (status >= 0) {
     for (int k = 0; k < root->q; ++k) { I_out[k] = root->I[k]; J_out[k] = root->J[k]; }
     if (root->is_short) status = ORC_ERR_RANK;

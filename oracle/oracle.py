@@ -66,6 +66,8 @@ def lib():
         L.oracle_tree_size.restype = i32
         L.oracle_cur_select.argtypes = [P, i64, i64, i64, i32, i32, dbl, i32, P, P, P, P, P, P, P]
         L.oracle_cur_select.restype = i32
+        L.oracle_cur_select_polish.argtypes = [P, i64, i64, i64, i32, i32, dbl, i32, P, P, P, P, P, P, P]
+        L.oracle_cur_select_polish.restype = i32
         L.oracle_cur_select_theta.argtypes = [P, i64, i64, i64, i32, i32, dbl, i32, dbl, P, P, P]
         L.oracle_cur_select_theta.restype = i32
         L.oracle_sm_row_update.argtypes = [P, i64, i32, i64, i32, P]
@@ -169,8 +171,10 @@ def n_leaves(n: int, w: int) -> int:
     return max(1, n // w)
 
 
-def select(A, r, w=0, tau=0.0, max_swaps=0, trace=False):
-    """Full partition-and-merge selection. Returns dict with I, J, status, info (+trace)."""
+def select(A, r, w=0, tau=0.0, max_swaps=0, trace=False, polish=False):
+    """Full partition-and-merge selection (with polish: then the swap loop on
+    all columns from the root's cross, oracle_cur_select_polish). Returns dict
+    with I, J, status, info (+trace)."""
     A = _f64(A)
     m, n = A.shape
     I = np.full(r, -1, dtype=np.int64)
@@ -179,14 +183,14 @@ def select(A, r, w=0, tau=0.0, max_swaps=0, trace=False):
     ww = w if w else max(64, r)
     args = [None, None, None, None]
     if trace and ww >= r:
-        N = lib().oracle_tree_size(n_leaves(n, ww))
+        N = lib().oracle_tree_size(n_leaves(n, ww)) + (1 if polish else 0)
         tm = np.zeros((N, TRACE_META), dtype=np.int64)
         tv = np.zeros(N)
         tI = np.zeros((N, r), dtype=np.int64)
         tJ = np.zeros((N, r), dtype=np.int64)
         args = [_p(tm), _p(tv), _p(tI), _p(tJ)]
-    rc = lib().oracle_cur_select(_p(A), m, n, n, r, int(w), float(tau), int(max_swaps), _p(I), _p(J),
-                                 ctypes.byref(info), *args)
+    fn = lib().oracle_cur_select_polish if polish else lib().oracle_cur_select
+    rc = fn(_p(A), m, n, n, r, int(w), float(tau), int(max_swaps), _p(I), _p(J), ctypes.byref(info), *args)
     out = {"status": rc, "I": I, "J": J, "rank": info.rank, "nodes": info.nodes,
            "phases": info.phases, "refreshes": info.refreshes, "swaps": info.swaps,
            "logvol": info.logvol}
