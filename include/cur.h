@@ -95,7 +95,15 @@ typedef struct {
                           NaN, cur_select_batched rejects it, and a trace (capacity >= 1)
                           receives one record whose I and J list the rows and columns in the
                           order chosen (q = rank reached, short = 1 if below r)               */
-  int32_t reserved1;
+  int32_t polish;      /* method 0, cur_select only: 0 none; 1 after the tree, the same swap loop
+                          once more on the whole matrix: every column is a candidate and the
+                          start is the root's cross, so that on return (status CUR_OK) every
+                          entry of A(:,J) A(I,J)^-1 and of A(I,J)^-1 A(I,:) is at most 1 + tau
+                          in magnitude (Sec. 1.1's condition on all of A).  Costs one more
+                          tree level with an m x n copy of A in the workspace; needs
+                          r * n < 2^31.  A trace gets one more record (the level after the
+                          root, index 0).  A rank-short root is returned as it is, with no
+                          further record and no node counted.                              */
 } cur_opts;
 
 typedef struct {

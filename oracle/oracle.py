@@ -184,7 +184,7 @@ def select(A, r, w=0, tau=0.0, max_swaps=0, trace=False, polish=False):
     args = [None, None, None, None]
     if trace and ww >= r:
         N = lib().oracle_tree_size(n_leaves(n, ww)) + (1 if polish else 0)
-        tm = np.zeros((N, TRACE_META), dtype=np.int64)
+        tm = np.full((N, TRACE_META), -1, dtype=np.int64)  # rows left at level -1 were not written
         tv = np.zeros(N)
         tI = np.zeros((N, r), dtype=np.int64)
         tJ = np.zeros((N, r), dtype=np.int64)
@@ -195,7 +195,8 @@ def select(A, r, w=0, tau=0.0, max_swaps=0, trace=False, polish=False):
            "phases": info.phases, "refreshes": info.refreshes, "swaps": info.swaps,
            "logvol": info.logvol}
     if trace and ww >= r:
-        out["trace"] = {"meta": tm, "vol_m": tv, "I": tI, "J": tJ}
+        k = int(np.count_nonzero(tm[:, 0] >= 0))  # records are written in order
+        out["trace"] = {"meta": tm[:k], "vol_m": tv[:k], "I": tI[:k], "J": tJ[:k]}
     return out
 
 

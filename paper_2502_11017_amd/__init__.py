@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("max_swaps", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("propose", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("seed", ctypes.c_uint64),
-                ("trace", ctypes.POINTER(Trace)), ("method", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("trace", ctypes.POINTER(Trace)), ("method", ctypes.c_int32), ("polish", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -196,11 +196,12 @@ def _matrix(A):
 
 
 def make_opts(col_block=0, tau=0.0, max_swaps=0, prec=PREC_NATIVE, trace=None, groups=0, method=0,
-              mlp=None, seed=0) -> Opts:
+              mlp=None, seed=0, polish=False) -> Opts:
     o = Opts()
     lib().cur_opts_init(ctypes.byref(o))
     o.groups = int(groups)
     o.method = int(method)
+    o.polish = 1 if polish else 0
     if mlp is not None:  # a device tensor holding the weight blob: the learned proposal
         o.propose = 1
         o.mlp = ctypes.c_void_p(mlp.data_ptr())
@@ -225,8 +226,10 @@ def tree_size(n: int, w: int) -> int:
 
 
 def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, trace: bool = False,
-           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0, method: int = METHOD_MAXVOL, mlp=None, seed: int = 0):
-    """Select r rows I and r columns J of the device matrix A (cur_select)."""
+           allow=(OK, WARN_NOCONV, ERR_RANK), groups: int = 0, method: int = METHOD_MAXVOL, mlp=None, seed: int = 0,
+           polish: bool = False):
+    """Select r rows I and r columns J of the device matrix A (cur_select);
+    polish: then the swap loop once more over all columns (cur_opts.polish)."""
     torch = _torch()
     m, n, lda = _matrix(A)
     ctx = context(A.device.index)
@@ -239,12 +242,13 @@ def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, 
         import numpy as np
 
         w = col_block if col_block else max(64, r)
-        N = 1 if method == METHOD_GREEDY else tree_size(n, max(w, 1))
+        N = 1 if method == METHOD_GREEDY else tree_size(n, max(w, 1)) + (1 if polish else 0)
         host = {"meta": np.zeros((N, 10), dtype=np.int64), "vol_m": np.zeros(N),
                 "I": np.zeros((N, r), dtype=np.int64), "J": np.zeros((N, r), dtype=np.int64)}
         tr = Trace(N, 0, host["meta"].ctypes.data, host["vol_m"].ctypes.data,
                    host["I"].ctypes.data, host["J"].ctypes.data)
-    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups, method=method, mlp=mlp, seed=seed)
+    o = make_opts(col_block, tau, max_swaps, trace=tr, groups=groups, method=method, mlp=mlp, seed=seed,
+                  polish=polish)
     rc = lib().cur_select(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r,
                           ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                           ctypes.byref(info))
@@ -252,8 +256,8 @@ def select(A, r: int, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, 
     out = {"I": I, "J": J, "status": rc, "rank": info.rank, "nodes": info.nodes,
            "phases": info.phases, "refreshes": info.refreshes, "swaps": info.swaps,
            "logvol": info.logvol}
-    if trace:
-        out["trace"] = host
+    if trace:  # the records the library wrote (a polish over a rank-short root writes none)
+        out["trace"] = {k: v[:tr.count] for k, v in host.items()}
     return out
 
 

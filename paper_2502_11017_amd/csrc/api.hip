@@ -94,6 +94,9 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
   if (o.groups < 0 || o.groups > 3) return arg_error("groups must be 0 (autotuned) or 1..3");
   if (o.method != 0 && o.method != 1) return arg_error("method must be 0 (maximal volume) or 1 (norm-greedy)");
   if (o.propose == 0 && o.mlp != nullptr) return arg_error("mlp must be NULL when propose == 0");
+  if (o.polish != 0 && o.polish != 1) return arg_error("polish must be 0 or 1");
+  if (o.polish == 1 && o.method != 0) return arg_error("polish == 1 applies to the maximal-volume method only");
+  if (o.polish == 1 && (int64_t)r * n > 0x7fffffff) return arg_error("polish == 1 needs r * n < 2^31");
   if (o.trace) {
     int64_t b = n / o.col_block;
     if (b < 1) b = 1;
@@ -104,6 +107,7 @@ static cur_status resolve_opts(const cur_opts* in, cur_dtype dtype, int32_t r, i
       c = (c + 1) / 2;
     }
     if (o.method == 1) tot = 1;  // one record: the choice orders
+    else if (o.polish == 1) tot += 1;  // the polish record
     if (!o.trace->meta || !o.trace->vol_mant || !o.trace->I || !o.trace->J)
       return arg_error("cur_trace arrays must be non-NULL");
     if (o.trace->capacity < tot) return arg_error("cur_trace.capacity too small for the tree");
@@ -311,6 +315,7 @@ cur_status cur_select_rect(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t
   if (st != CUR_OK) return st;
   if (o.trace) return arg_error("cur_select_rect takes no trace");
   if (o.propose != 0) return arg_error("cur_select_rect takes no learned proposal");
+  if (o.polish != 0) return arg_error("cur_select_rect takes no polish");
   if (!ctx) return arg_error("ctx is NULL");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");
@@ -462,6 +467,8 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
     return arg_error("batched selection supports the maximal-volume method only");
   if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->propose != 0)
     return arg_error("batched selection supports no candidate proposal");
+  if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->polish != 0)
+    return arg_error("batched selection supports no polish");
   for (int32_t i = 0; i < count; ++i) {
     const cur_item& it = items[i];
     cur_status st = check_matrix(it.dtype, it.A, it.m, it.n, it.lda, it.r);

@@ -30,7 +30,9 @@ enum NodeState : int32_t {
   ST_START_SWAP = 4, // next ctl: start the swap loop (ROW phase start)
 };
 
-enum NodeKind : int32_t { KIND_LEAF = 0, KIND_MERGE = 1, KIND_PROMOTED = 2 };
+// KIND_POLISH: one node after a tree's root whose candidates are all n columns,
+// started from the root's cross (cur_opts.polish).
+enum NodeKind : int32_t { KIND_LEAF = 0, KIND_MERGE = 1, KIND_PROMOTED = 2, KIND_POLISH = 3 };
 
 // Winner of one row tile in a pass.
 struct Partial {

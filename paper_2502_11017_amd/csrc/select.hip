@@ -86,13 +86,15 @@ __global__ __launch_bounds__(kThreads) void k_amax(const ScanItem* __restrict__ 
 }
 
 // ---------------------------------------------------------------- leaf set-up
-// panel(:, c) = A(:, c0 + c) for each leaf's block (the leaf's own matrix),
+// panel(:, c) = A(:, c0 + c) for each leaf's block (the leaf's own matrix; a
+// polish node's block is every column),
 // transposed through LDS.  grid (row tiles, column tiles of 64, leaves).  A
 // tree over A^T (trans) reads panel column c from row c0 + c of the source,
 // which is already contiguous (lanes along it).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_panel_from_A(Node* nodes) {
   Node& nd = nodes[blockIdx.z];
+  if (nd.kind != KIND_LEAF && nd.kind != KIND_POLISH) return;
   const int64_t m = nd.m;
   const int nc = nd.nc;
   const int64_t r0 = (int64_t)blockIdx.x * kTR;
@@ -144,6 +146,34 @@ __global__ __launch_bounds__(kThreads) void k_merge_init(Node* nodes, const Node
   Node& nd = nodes[blockIdx.x];
   const int tid = threadIdx.x;
   const int r = nd.r;
+  if (nd.kind == KIND_POLISH) {
+    // candidates: every column (Jc the identity); start: the root's cross,
+    // J as positions in Jc, i.e. original indices; a rank-short or failed
+    // root is passed on unchanged
+    const Node& c = prev[nd.child0];
+    for (int cc = tid; cc < nd.nc; cc += blockDim.x) {
+      nd.Jc[cc] = cc;
+      nd.colmap[cc] = cc;
+    }
+    const int q = c.q;
+    for (int k = tid; k < q; k += blockDim.x) {
+      nd.I[k] = c.I[k];
+      nd.Jp[k] = (int32_t)c.Jc[c.Jp[k]];
+    }
+    if (tid == 0) {
+      nd.q = q;
+      nd.t = q;
+      nd.is_short = c.is_short;
+      nd.vol_m = c.vol_m;
+      nd.vol_e = c.vol_e;
+      nd.err = c.err;
+      nd.swaps = nd.phases = nd.refreshes = 0;
+      nd.nocap = 0;
+      nd.phase = nd.phase_swaps = nd.since = 0;
+      nd.st = (c.is_short || c.err) ? ST_DONE : ST_START_SWAP;
+    }
+    return;
+  }
   if (nd.kind == KIND_PROMOTED) {
     const Node& c = prev[nd.child0];
     for (int k = tid; k < r; k += blockDim.x) {
@@ -1411,6 +1441,7 @@ struct TreeJob {
   int64_t* J;
   cur_info* info;
   bool trans = false;       // select from A^T: m, n are A^T's shape, A and lda the source's
+  bool polish = false;      // one more level: the root's cross polished over all n columns
   cur_status status = CUR_OK;
   bool active = true;
   double theta = 0.0;
@@ -1506,6 +1537,10 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     }
     jb.ncmax.assign(jb.count.size(), 2 * jb.r);
     jb.ncmax[0] = jb.leafmax;
+    if (jb.polish) {
+      jb.count.push_back(1);
+      jb.ncmax.push_back((int)jb.n);
+    }
     nlev = std::max<int>(nlev, (int)jb.count.size());
   }
   if (nlev == 0) return CUR_OK;  // every tree ended at the scan
@@ -1526,9 +1561,12 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
 
   // ---- workspace layout
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  // the polish level starts from a cross (no elimination on its candidates):
+  // its working matrix holds B only
+  auto is_polish = [](const TreeJob<T>& jb, int l) { return jb.polish && l + 1 == (int)jb.count.size(); };
   auto node_bytes = [&](const TreeJob<T>& jb, int l) {
     const int nc = jb.ncmax[l], r = jb.r;
-    const int wd = std::max(nc, r);
+    const int wd = is_polish(jb, l) ? r : std::max(nc, r);
     const int64_t m = jb.m;
     size_t per = 0;
     per += al(sizeof(T) * m * nc);                // panel
@@ -1581,7 +1619,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     iter_bound = std::max<int64_t>(iter_bound, 16 * (int64_t)(r + 4) + 8 * (int64_t)jb.o.max_swaps + 4096);
     for (size_t l = 0; l < jb.count.size(); ++l) {
       const int nc = jb.ncmax[l];
-      const int wd = std::max(nc, r);
+      const int wd = is_polish(jb, (int)l) ? r : std::max(nc, r);
       for (int k = 0; k < jb.count[l]; ++k) {
         Node& nd = h[lfirst[l] + jb.off[l] + k];
         nd.m = jb.m;
@@ -1623,6 +1661,16 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
           nd.lda = jb.lda;
           nd.trans = jb.trans ? 1 : 0;
           nd.col0 = c0;
+        } else if (is_polish(jb, (int)l)) {
+          nd.kind = KIND_POLISH;
+          nd.child0 = jb.off[l - 1];
+          nd.child1 = -1;
+          nd.nc = (int)jb.n;
+          nd.src = jb.A;
+          nd.lda = jb.lda;
+          nd.trans = jb.trans ? 1 : 0;
+          nd.col0 = 0;
+          nd.st = ST_DONE;
         } else {
           const int pc = jb.count[l - 1], po = jb.off[l - 1];
           if (2 * k + 1 < pc) {
@@ -1702,6 +1750,12 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev);
     const int gx = (int)std::min<int64_t>((lm + kThreads - 1) / kThreads, 64);
     hipLaunchKernelGGL((k_panel_build<T>), dim3(gx, 2 * rmax, cnt), dim3(kThreads), 0, s, cur, prev);
+    int64_t polish_n = 0;  // a polish node's panel: every column of its matrix
+    for (const TreeJob<T>& jb : jobs)
+      if (jb.active && jb.polish && (int)jb.count.size() == l + 1) polish_n = std::max(polish_n, jb.n);
+    if (polish_n > 0)
+      hipLaunchKernelGGL((k_panel_from_A<T>), dim3((lm + kTR - 1) / kTR, (unsigned)((polish_n + 63) / 64), cnt),
+                         dim3(kThreads), 0, s, cur);
     const int64_t key[6] = {f64, rb, cnt, lt, lm, 0};
     int cand = -1;
     const int groups = tune_pick(ctx, key, fixed_groups, &cand);
@@ -1756,9 +1810,18 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     }
 
   // ---- per-tree results
+  auto polish_idle = [&](const TreeJob<T>& jb) {
+    if (!jb.polish) return false;
+    const size_t l = jb.count.size() - 2;  // the tree's root, the polish node's start
+    const Node& c = h[lfirst[l] + jb.off[l]];
+    return c.is_short != 0 || c.err != 0;
+  };
   for (TreeJob<T>& jb : jobs) {
     if (!jb.active) continue;
     auto node = [&](size_t l, int k) -> const Node& { return h[lfirst[l] + jb.off[l] + k]; };
+    // a polish level over a rank-short or failed root did nothing: no node,
+    // no counters, no trace record
+    const bool pol_idle = polish_idle(jb);
     cur_status result = CUR_OK;
     int32_t nodes = 0, phases = 0, refreshes = 0;
     int64_t swaps = 0;
@@ -1772,7 +1835,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
           where = " (level " + std::to_string(l) + " node " + std::to_string(k) + " code " + std::to_string(nd.err) +
                   " phase " + std::to_string(nd.phase) + " swaps " + std::to_string(nd.swaps) + ")";
         }
-        if (nd.kind == KIND_PROMOTED) continue;
+        if (nd.kind == KIND_PROMOTED || (pol_idle && nd.kind == KIND_POLISH)) continue;
         nodes++;
         phases += nd.phases;
         refreshes += nd.refreshes;
@@ -1803,12 +1866,17 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   if (tr && jobs[0].active) {
     const TreeJob<T>& jb = jobs[0];
     const int cap = tr->capacity;
+    const bool pol_idle = polish_idle(jb);
     int slot = 0;
     for (size_t l = 0; l < jb.count.size(); ++l)
       for (int k = 0; k < jb.count[l]; ++k, ++slot) {
-        if (slot >= cap) continue;
         const size_t gi = lfirst[l] + jb.off[l] + k;
         const Node& nd = h[gi];
+        if (pol_idle && nd.kind == KIND_POLISH) {
+          --slot;
+          continue;
+        }
+        if (slot >= cap) continue;
         int64_t* mt = tr->meta + (size_t)slot * kMetaFields;
         const bool pr = nd.kind == KIND_PROMOTED;
         mt[0] = (int64_t)l;
@@ -1827,7 +1895,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
           tr->J[(size_t)slot * rtr + j] = eJ[gi * rtr + j];
         }
       }
-    tr->count = total;
+    tr->count = slot;
   }
   return CUR_OK;
 }
@@ -1846,6 +1914,7 @@ static cur_status select_one(cur_ctx ctx, const T* A, int64_t m, int64_t n, int6
   jb.I = I;
   jb.J = J;
   jb.info = info;
+  jb.polish = o.polish != 0;
   cur_status rc = select_many<T>(ctx, rmax_bucket(r), jobs, o.trace);
   if (rc != CUR_OK) return rc;
   return jobs[0].status;

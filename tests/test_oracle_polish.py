@@ -63,8 +63,10 @@ def test_polish_of_a_dominant_root_makes_no_swap(orc):
 
 def test_polish_leaves_a_rank_short_root(orc):
     A = rand(40, 3, 5) @ rand(3, 60, 6)  # rank 3
-    base = orc.select(A, 5, w=8)
-    pol = orc.select(A, 5, w=8, polish=True)
+    base = orc.select(A, 5, w=8, trace=True)
+    pol = orc.select(A, 5, w=8, polish=True, trace=True)
     assert base["status"] == pol["status"] == orc.ERR_RANK
     np.testing.assert_array_equal(base["I"], pol["I"])
     assert pol["nodes"] == base["nodes"]
+    # no polish record either
+    np.testing.assert_array_equal(pol["trace"]["meta"], base["trace"]["meta"])
