@@ -452,29 +452,62 @@ __device__ __forceinline__ double ctl_x(const CtlLds<T, RMAX>& L, int r, int a, 
 }
 
 // Fresh column interpolation matrix Bc = X A(I, Jc) (r x nc, row-major, ld ncmax),
-// sums over k ascending, then column Jp[k] := e_k.  X is in L.A.
+// sums over k ascending, then column Jp[k] := e_k.  X is in L.A.  Chunks of
+// CH columns: A(I, chunk) staged in L.B (a polish node reads the rows of its
+// source matrix, contiguous along the chunk, instead of its column-major
+// panel), then thread (g, j) forms outputs (g + G q, j), q < QM, each a
+// register accumulator over k, so one L.B read serves QM products.
 template <typename T, int RMAX>
 __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
-  const int r = nd.r, nc = L.s.nc, ld = nd.ncmax;
+  const int r = nd.r, nc = L.s.nc, ld = nd.ncmax, tid = threadIdx.x;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
+  const T* S = (nd.kind == KIND_POLISH && !nd.trans) ? (const T*)nd.src : nullptr;
+  const int64_t lds = nd.lda;
   constexpr int CH = CtlLds<T, RMAX>::CH;
+  constexpr int G = kThreads / CH;            // row groups
+  constexpr int QM = (RMAX + G - 1) / G;      // outputs per thread
+  static_assert(kThreads % CH == 0, "column chunk must divide the block");
+  constexpr int GL = (RMAX * CH + kThreads - 1) / kThreads;  // staged elements per thread
+  const int j = tid % CH, g = tid / CH;
   for (int c0 = 0; c0 < nc; c0 += CH) {
     const int nb = min(CH, nc - c0);
-    for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
-      const int k = idx / nb, j = idx % nb;
-      L.B[k * CH + j] = (double)P[(int64_t)(c0 + j) * m + L.sI[k]];
+    // A(I, chunk): this thread's elements e = k CH + jj, all loads issued
+    // before the first LDS store (clamped indices; stored only if in range)
+    double st[GL];
+#pragma unroll
+    for (int q = 0; q < GL; ++q) {
+      const int e = tid + q * kThreads;
+      const int k = min(e / CH, r - 1), jj = min(e % CH, nb - 1);
+      st[q] = S ? (double)S[L.sI[k] * lds + c0 + jj] : (double)P[(int64_t)(c0 + jj) * m + L.sI[k]];
+    }
+#pragma unroll
+    for (int q = 0; q < GL; ++q) {
+      const int e = tid + q * kThreads;
+      if (e < r * CH && e % CH < nb) L.B[e] = st[q];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < r * nb; idx += kThreads) {
-      const int a = idx / nb, j = idx % nb;
-      double s = 0.0;
-      for (int k = 0; k < r; ++k) s = fma(ctl_x(L, r, a, k), L.B[k * CH + j], s);
-      bc[(int64_t)a * ld + c0 + j] = s;
+    if (j < nb) {
+      double acc[QM];
+#pragma unroll
+      for (int q = 0; q < QM; ++q) acc[q] = 0.0;
+      for (int k = 0; k < r; ++k) {
+        const double b = L.B[k * CH + j];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+          const int a = min(g + G * q, r - 1);
+          acc[q] = fma(ctl_x(L, r, a, k), b, acc[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        const int a = g + G * q;
+        if (a < r) bc[(int64_t)a * ld + c0 + j] = acc[q];
+      }
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
+  for (int idx = tid; idx < r * r; idx += kThreads) {
     const int k = idx / r, a = idx % r;
     bc[(int64_t)a * ld + L.sJp[k]] = (a == k) ? 1.0 : 0.0;
   }
@@ -498,14 +531,87 @@ __device__ void ctl_load_X(Node& nd, CtlLds<T, RMAX>& L) {
   }
 }
 
+// Elements of the r x nc matrix Bc visited by one thread: flat index
+// e = a nc + c (row-major, so the lanes of a wavefront read consecutive
+// columns of one row), e = tid + kThreads i, in batches of kColU whose loads
+// are issued before any is used.  The (a, c) pair advances by a fixed step;
+// past the end, the row is clamped to r - 1 and the element marked invalid.
+constexpr int kColU = 8;
+
+struct ColWalk {
+  int a, c, sa, sc, nc, r, tot, e;
+  __device__ ColWalk(int r_, int nc_, int tid) : nc(nc_), r(r_), tot(r_ * nc_), e(tid) {
+    a = tid / nc_;
+    c = tid - a * nc_;
+    sa = kThreads / nc_;
+    sc = kThreads - sa * nc_;
+  }
+  __device__ bool more() const { return e < tot; }
+  // positions of the next batch
+  __device__ void batch(int (&ra)[kColU], int (&rc)[kColU], bool (&ok)[kColU]) {
+#pragma unroll
+    for (int u = 0; u < kColU; ++u) {
+      ok[u] = e + u * kThreads < tot;
+      ra[u] = min(a, r - 1);
+      rc[u] = c;
+      c += sc;
+      a += sa;
+      if (c >= nc) {
+        c -= nc;
+        ++a;
+      }
+    }
+    e += kColU * kThreads;
+  }
+};
+
 // The whole COL phase of one node (maxvol on A(I, Jc)^T with I fixed).
-// Returns after the phase; L.s.mode is set to the follow-up.
+// Returns after the phase; L.s.mode is set to the follow-up.  The argmax is
+// over |Bc(a, c)| for columns c not in J, ties to the smaller column-major key
+// c r + a, so the order in which elements are visited does not matter; each
+// swap's rank-one update also forms the next argmax on the values it writes.
 template <typename T, int RMAX>
 __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
+  const int64_t tph = wall_clock64();
   const int r = nd.r, nc = L.s.nc, ld = nd.ncmax, tid = threadIdx.x;
   double* bc = ((int64_t)r * ld <= CtlLds<T, RMAX>::BCCAP) ? L.Bcl : nd.Bc;
   uint8_t* insel = (nc <= CtlLds<T, RMAX>::INSCAP) ? L.insel : nd.insel;
   const int guard_max = 4 * nd.smax + 16;
+  auto make = [&](double x, int a, int c) {
+    Cand o;
+    o.val = fabs(x);
+    o.sval = x;
+    o.key = (int64_t)c * r + a;
+    o.row = a;
+    o.pos = c;
+    return o;
+  };
+  // argmax over the columns not in J
+  auto fresh = [&]() {
+    const int64_t tf = wall_clock64();
+    ctl_fresh_bc(nd, L, bc);
+    if (tid == 0) nd.tclk[2] += wall_clock64() - tf;
+  };
+  auto scan = [&]() {
+    Cand b = cand_none();
+    ColWalk w(r, nc, tid);
+    while (w.more()) {
+      int ra[kColU], rc[kColU];
+      bool ok[kColU];
+      w.batch(ra, rc, ok);
+      double x[kColU];
+      uint8_t f[kColU];
+#pragma unroll
+      for (int u = 0; u < kColU; ++u) {
+        x[u] = bc[(int64_t)ra[u] * ld + rc[u]];
+        f[u] = insel[rc[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kColU; ++u)
+        if (ok[u] && !f[u]) cand_take(b, make(x[u], ra[u], rc[u]));
+    }
+    return block_argmax(b, L.sc);
+  };
   ctl_sort_IJ(nd, L, r);
   if (tid == 0) {
     L.s.phase_swaps = 0;
@@ -522,29 +628,19 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
       if (tid == 0) L.s.err = 101;
     } else {
       ctl_load_X(nd, L);
-      ctl_fresh_bc(nd, L, bc);
+      fresh();
       if (tid == 0) L.s.refreshes++;
       __syncthreads();
+      Cand b = cand_none();
+      bool have = false;  // b already formed by the last update
       for (int guard = 0;; ++guard) {
         if (guard >= guard_max) {
           if (tid == 0) L.s.err = 102;
           __syncthreads();
           break;
         }
-        Cand b = cand_none();
-        for (int idx = tid; idx < r * nc; idx += kThreads) {
-          const int c = idx / r, k = idx % r;
-          if (insel[c]) continue;
-          const double x = bc[(int64_t)k * ld + c];
-          Cand o;
-          o.val = fabs(x);
-          o.sval = x;
-          o.key = (int64_t)c * r + k;
-          o.row = k;
-          o.pos = c;
-          cand_take(b, o);
-        }
-        b = block_argmax(b, L.sc);
+        if (!have) b = scan();
+        have = false;
         if (b.row < 0 || b.val <= lim) {
           if (L.s.since == 0) break;
           if (!ctl_build(nd, L, true, false)) {
@@ -552,7 +648,7 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
             break;
           }
           ctl_load_X(nd, L);
-          ctl_fresh_bc(nd, L, bc);
+          fresh();
           if (tid == 0) {
             L.s.refreshes++;
             L.s.since = 0;
@@ -566,7 +662,9 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
           break;
         }
         // swap candidate column c* into slot k*
+        const int64_t tsw = wall_clock64();
         const int ks = (int)b.row, cs = b.pos;
+        const int cold = L.sJp[ks];  // the column leaving J
         const double p = b.sval;
         double* wv = L.wv;                // w (r)
         double* rowk = (nc <= CtlLds<T, RMAX>::ROWKCAP) ? L.rowk : nd.vec + RMAX;  // old row k*
@@ -577,21 +675,47 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
         for (int c = tid; c < nc; c += kThreads) rowk[c] = bc[(int64_t)ks * ld + c];
         if (rowk == L.rowk) __syncthreads();
         else block_global_sync();
-        for (int idx = tid; idx < r * nc; idx += kThreads) {
-          const int a = idx / nc, c = idx % nc;
-          double x = fma(-wv[a], rowk[c], bc[(int64_t)a * ld + c]);
-          if (c == cs) x = (a == ks) ? 1.0 : 0.0;
-          bc[(int64_t)a * ld + c] = x;
+        // Bc -= w rowk^T, column c* := e_k*; the next argmax on the new values
+        // with J' = J - {c_old} + {c*}
+        Cand nb = cand_none();
+        {
+          ColWalk w(r, nc, tid);
+          while (w.more()) {
+            int ra[kColU], rc[kColU];
+            bool ok[kColU];
+            w.batch(ra, rc, ok);
+            double x[kColU], rk[kColU];
+            uint8_t f[kColU];
+#pragma unroll
+            for (int u = 0; u < kColU; ++u) {
+              x[u] = bc[(int64_t)ra[u] * ld + rc[u]];
+              rk[u] = rowk[rc[u]];
+              f[u] = insel[rc[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kColU; ++u) {
+              double y = fma(-wv[ra[u]], rk[u], x[u]);
+              if (rc[u] == cs) y = (ra[u] == ks) ? 1.0 : 0.0;
+              if (ok[u]) {
+                bc[(int64_t)ra[u] * ld + rc[u]] = y;
+                const bool in = rc[u] == cs || (f[u] && rc[u] != cold);
+                if (!in) cand_take(nb, make(y, ra[u], rc[u]));
+              }
+            }
+          }
         }
         if (bc == L.Bcl) __syncthreads();
         else block_global_sync();
+        b = block_argmax(nb, L.sc);
+        have = true;
         if (tid == 0) {
-          insel[L.sJp[ks]] = 0;
+          insel[cold] = 0;
           insel[cs] = 1;
           L.sJp[ks] = cs;
           L.s.swaps++;
           L.s.phase_swaps++;
           L.s.since++;
+          nd.tclk[3] += wall_clock64() - tsw;
         }
         if (insel == L.insel) __syncthreads();
         else block_global_sync();
@@ -599,6 +723,7 @@ __device__ void ctl_col_phase(Node& nd, CtlLds<T, RMAX>& L, double lim) {
     }
   }
   __syncthreads();
+  if (tid == 0) nd.tclk[1] += wall_clock64() - tph;
   if (tid == 0) {
     L.s.phases++;
     if (L.s.err || L.s.nocap || L.s.phase_swaps == 0) {

@@ -59,6 +59,28 @@ def test_fullsize_f64_selection_matches_oracle(orc, c2_pair):
     assert np.abs(row_interp(Ah, o["I"], o["J"])).max() <= 1 + 1e-12
 
 
+def test_fullsize_polish_matches_oracle(orc, c2_pair):
+    """The optional whole-matrix polish at full size: one more node over all
+    8192 columns (candidate flags and Bc beyond the controller's LDS); index
+    sets and counters equal the oracle's, and the cross is dominant over every
+    column."""
+    A, Ah, _ = c2_pair
+    say("  oracle selection with polish (~20 s)")
+    o = orc.select(Ah, R, polish=True)
+    g = cur.select(A, R, polish=True)
+    say(f"  gpu status {g['status']} swaps {g['swaps']} (oracle {o['swaps']}), logvol {g['logvol']:.6f}")
+    assert g["status"] == o["status"] == cur.OK
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    for key in ("rank", "nodes", "phases", "refreshes", "swaps"):
+        assert g[key] == o[key], (key, g[key], o[key])
+    assert abs(g["logvol"] - o["logvol"]) <= 1e-12 * abs(o["logvol"])
+    I, J = o["I"], o["J"]
+    assert np.abs(row_interp(Ah, I, J)).max() <= 1 + 1e-12
+    X = np.linalg.solve(Ah[np.ix_(I, J)], Ah[I, :])  # A(I,J)^-1 A(I,:), every column
+    assert np.abs(X).max() <= 1 + 1e-12
+
+
 def test_fullsize_f64_assembly_and_residual(orc, c2_pair):
     A, Ah, o = c2_pair
     I = torch.from_numpy(o["I"]).to(DEV)
