@@ -95,7 +95,7 @@ typedef struct {
                           NaN, cur_select_batched rejects it, and a trace (capacity >= 1)
                           receives one record whose I and J list the rows and columns in the
                           order chosen (q = rank reached, short = 1 if below r)               */
-  int32_t polish;      /* method 0, cur_select only: 0 none; 1 after the tree, the same swap loop
+  int32_t polish;      /* method 0: 0 none; 1 after the tree, the same swap loop
                           once more on the whole matrix: every column is a candidate and the
                           start is the root's cross, so that on return (status CUR_OK) every
                           entry of A(:,J) A(I,J)^-1 and of A(I,J)^-1 A(I,:) is at most 1 + tau
@@ -103,7 +103,10 @@ typedef struct {
                           tree level with an m x n copy of A in the workspace; needs
                           r * n < 2^31.  A trace gets one more record (the level after the
                           root, index 0).  A rank-short root is returned as it is, with no
-                          further record and no node counted.                              */
+                          further record and no node counted.  cur_select_rect with r == c:
+                          the same loop on the cross (I, J) of its two trees (the symmetric
+                          form of Alg. 2), skipped if either tree falls short; info.logvol
+                          is then that cross's.  cur_select_batched rejects it.          */
 } cur_opts;
 
 typedef struct {
@@ -249,6 +252,10 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
  * reached are -1), else CUR_WARN_NOCONV if either tree spent its swap budget.
  * info (nullable): rank = the smaller of the two ranks reached, swaps /
  * phases / refreshes / nodes summed over both trees, logvol NaN.
+ * opts->polish = 1 (method 0, r == c only, else CUR_ERR_ARG): then the swap
+ * loop on the square cross (I, J) of the two trees with every column a
+ * candidate, one more node whose counters are added to info; logvol is then
+ * log |det A(I,J)| of the result.  Skipped when either tree is rank-short.
  */
 cur_status cur_select_rect(cur_ctx ctx, int32_t dtype, const void* A, int64_t m, int64_t n, int64_t lda, int32_t r,
                            int32_t c, const cur_opts* opts, int64_t* I, int64_t* J, cur_info* info);

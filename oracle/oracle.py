@@ -379,17 +379,30 @@ def _worse(a, b):
     return a if a != OK else b
 
 
-def select_rect(A, r, c, method=0, w=0, tau=0.0, max_swaps=0):
+def select_rect(A, r, c, method=0, w=0, tau=0.0, max_swaps=0, polish=False):
     """Alg. 2 with separate counts: I (r rows) and J (c columns) chosen
     independently, each along its own axis.  method 0: J by the column-block
     maximal-volume tree on A with rank c, I by the same tree on A^T (row
     blocks of A) with rank r -- each tree's other index set is dropped;
-    method 1: the norm-greedy rule on rows and on columns (greedy_rc)."""
+    method 1: the norm-greedy rule on rows and on columns (greedy_rc).
+    polish (method 0, r == c): then the swap loop on the cross (I, J) with
+    every column a candidate (oracle_swap_loop), so that the square cross
+    meets Sec. 1.1's dominance condition on all of A; skipped when either
+    tree is rank-short or failed."""
     A = _f64(A)
     if method == 1:
         g = greedy_rc(A, r, c)
         return {"I": g["I"], "J": g["J"], "status": g["status"], "greedy": g}
     cols = select(A, c, w=w, tau=tau, max_swaps=max_swaps)
     rows = select(np.ascontiguousarray(A.T), r, w=w, tau=tau, max_swaps=max_swaps)
-    return {"I": rows["J"], "J": cols["J"], "status": _worse(rows["status"], cols["status"]),
-            "rows": rows, "cols": cols}
+    out = {"I": rows["J"], "J": cols["J"], "status": _worse(rows["status"], cols["status"]),
+           "rows": rows, "cols": cols}
+    if polish and r == c and out["status"] in (OK, WARN_NOCONV):
+        n = A.shape[1]
+        I, J, st = swap_loop(A, out["I"], out["J"], np.arange(n), tau=tau if tau else 1e-13,
+                             smax=max_swaps if max_swaps else 64 * r)
+        out["polish"] = st
+        out["I"], out["J"] = I, J
+        out["status"] = _worse(out["status"], st["status"])
+        out["logvol"] = logvol(A, I, J)
+    return out

@@ -298,21 +298,22 @@ def residual(A, C, U, R, prec: int = PREC_NATIVE):
 
 
 def select_rect(A, r: int, c: int, method: int = METHOD_MAXVOL, col_block: int = 0, tau: float = 0.0,
-                max_swaps: int = 0, groups: int = 0, allow=(OK, WARN_NOCONV, ERR_RANK)):
-    """r rows I and c columns J chosen independently (Alg. 2), cur_select_rect."""
+                max_swaps: int = 0, groups: int = 0, allow=(OK, WARN_NOCONV, ERR_RANK), polish: bool = False):
+    """r rows I and c columns J chosen independently (Alg. 2), cur_select_rect;
+    polish (r == c): then the swap loop on the cross over all columns."""
     torch = _torch()
     m, n, lda = _matrix(A)
     ctx = context(A.device.index)
     I = torch.empty(r, dtype=torch.int64, device=A.device)
     J = torch.empty(c, dtype=torch.int64, device=A.device)
     info = Info()
-    o = make_opts(col_block, tau, max_swaps, groups=groups, method=method)
+    o = make_opts(col_block, tau, max_swaps, groups=groups, method=method, polish=polish)
     rc = lib().cur_select_rect(ctx, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), m, n, lda, r, c,
                                ctypes.byref(o), ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                                ctypes.byref(info))
     _check(rc, allow)
     return {"I": I, "J": J, "status": rc, "rank": info.rank, "nodes": info.nodes, "phases": info.phases,
-            "refreshes": info.refreshes, "swaps": info.swaps}
+            "refreshes": info.refreshes, "swaps": info.swaps, "logvol": info.logvol}
 
 
 def assemble_rect(A, I, J):

@@ -315,7 +315,7 @@ cur_status cur_select_rect(cur_ctx ctx, int32_t dtype_in, const void* A, int64_t
   if (st != CUR_OK) return st;
   if (o.trace) return arg_error("cur_select_rect takes no trace");
   if (o.propose != 0) return arg_error("cur_select_rect takes no learned proposal");
-  if (o.polish != 0) return arg_error("cur_select_rect takes no polish");
+  if (o.polish != 0 && r != c) return arg_error("cur_select_rect: polish needs r == c");
   if (!ctx) return arg_error("ctx is NULL");
   CUR_HIP_CHECK(hipSetDevice(ctx->device));
   set_error("");

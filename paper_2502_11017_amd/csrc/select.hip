@@ -136,6 +136,15 @@ __global__ void k_leaf_init(Node* nodes) {
   }
 }
 
+// A node that starts from a given cross (r original row and column indices;
+// its candidate list is the identity, so J's positions are the indices).
+__global__ void k_start_cross(Node* nd, const int64_t* __restrict__ I, const int64_t* __restrict__ J) {
+  for (int k = threadIdx.x; k < nd->r; k += blockDim.x) {
+    nd->I[k] = I[k];
+    nd->Jp[k] = (int32_t)J[k];
+  }
+}
+
 // ---------------------------------------------------------------- merge set-up
 // One workgroup per node of the new level.  Promoted nodes copy their child.
 // Merges form Jc as the sorted union of the children's selected columns, the
@@ -1567,6 +1576,10 @@ struct TreeJob {
   cur_info* info;
   bool trans = false;       // select from A^T: m, n are A^T's shape, A and lda the source's
   bool polish = false;      // one more level: the root's cross polished over all n columns
+  // a one-node job that polishes a given cross (device arrays of r original
+  // indices) over all n columns instead of selecting one
+  const int64_t* start_I = nullptr;
+  const int64_t* start_J = nullptr;
   cur_status status = CUR_OK;
   bool active = true;
   double theta = 0.0;
@@ -1688,7 +1701,9 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   // the polish level starts from a cross (no elimination on its candidates):
   // its working matrix holds B only
-  auto is_polish = [](const TreeJob<T>& jb, int l) { return jb.polish && l + 1 == (int)jb.count.size(); };
+  auto is_polish = [](const TreeJob<T>& jb, int l) {
+    return (jb.polish && l + 1 == (int)jb.count.size()) || jb.start_I != nullptr;
+  };
   auto node_bytes = [&](const TreeJob<T>& jb, int l) {
     const int nc = jb.ncmax[l], r = jb.r;
     const int wd = is_polish(jb, l) ? r : std::max(nc, r);
@@ -1786,6 +1801,11 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
           nd.lda = jb.lda;
           nd.trans = jb.trans ? 1 : 0;
           nd.col0 = c0;
+          if (jb.start_I) {  // the given cross, loaded by k_start_cross
+            nd.kind = KIND_POLISH;
+            nd.st = ST_START_SWAP;
+            nd.t = nd.q = r;
+          }
         } else if (is_polish(jb, (int)l)) {
           nd.kind = KIND_POLISH;
           nd.child0 = jb.off[l - 1];
@@ -1838,6 +1858,10 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   {
     const int b = lcount[0];
     hipLaunchKernelGGL(k_leaf_init, dim3(b), dim3(kThreads), 0, s, d_nodes);
+    for (const TreeJob<T>& jb : jobs)
+      if (jb.active && jb.start_I)
+        hipLaunchKernelGGL(k_start_cross, dim3(1), dim3(kThreads), 0, s, d_nodes + lfirst[0] + jb.off[0], jb.start_I,
+                           jb.start_J);
     hipLaunchKernelGGL((k_panel_from_A<T>), dim3((maxm + kTR - 1) / kTR, (leafmax + 63) / 64, b), dim3(kThreads),
                        0, s, d_nodes);
     if (propose) {  // learned candidates: the restricted start of every leaf that admits one
@@ -2099,9 +2123,44 @@ static cur_status select_rect_impl(cur_ctx ctx, const T* A, int64_t m, int64_t n
     info->nodes += inf[1].nodes;
     info->logvol = std::nan("");  // no single square cross
   }
-  for (cur_status s : {CUR_ERR_RANK, CUR_WARN_NOCONV})
-    if (jobs[0].status == s || jobs[1].status == s) return s;
-  return jobs[0].status != CUR_OK ? jobs[0].status : jobs[1].status;
+  auto worse = [](cur_status a, cur_status b) {
+    for (cur_status s : {CUR_ERR_RANK, CUR_WARN_NOCONV})
+      if (a == s || b == s) return s;
+    return a != CUR_OK ? a : b;
+  };
+  cur_status res = worse(jobs[0].status, jobs[1].status);
+  // r == c: the swap loop once more on the cross (I, J) of the two trees,
+  // every column a candidate; skipped when either tree fell short or failed
+  if (o.polish && r == c && (res == CUR_OK || res == CUR_WARN_NOCONV)) {
+    std::vector<TreeJob<T>> pj(1);
+    TreeJob<T>& jb = pj[0];
+    cur_info pinf{};
+    jb.A = A;
+    jb.m = m;
+    jb.n = n;
+    jb.lda = lda;
+    jb.r = r;
+    jb.o = o;
+    jb.o.trace = nullptr;
+    jb.o.col_block = (int32_t)n;  // one node over every column
+    jb.I = I;
+    jb.J = J;
+    jb.info = &pinf;
+    jb.start_I = I;
+    jb.start_J = J;
+    rc = select_many<T>(ctx, rmax_bucket(r), pj, nullptr);
+    if (rc != CUR_OK) return rc;
+    if (info) {
+      info->rank = pinf.rank;
+      info->swaps += pinf.swaps;
+      info->phases += pinf.phases;
+      info->refreshes += pinf.refreshes;
+      info->nodes += pinf.nodes;
+      info->logvol = pinf.logvol;
+    }
+    res = worse(res, pj[0].status);
+  }
+  return res;
 }
 
 cur_status select_rect_dispatch(cur_ctx ctx, cur_dtype dtype, const void* A, int64_t m, int64_t n, int64_t lda,

@@ -204,8 +204,9 @@ def test_rect_argument_errors_on_host():
 
 
 def test_polish_option_errors_on_host():
-    """cur_opts.polish: 0 or 1, the maximal-volume method, cur_select only,
-    r * n < 2^31; all checked before any device work."""
+    """cur_opts.polish: 0 or 1, the maximal-volume method, cur_select or
+    cur_select_rect with r == c, r * n < 2^31; all checked before any device
+    work."""
     L = cur.lib()
     p = ctypes.c_void_p(1)
     o = cur.make_opts()
@@ -217,7 +218,9 @@ def test_polish_option_errors_on_host():
     assert _sel(m=64, n=1 << 26, lda=1 << 26, r=64, opts=o) == cur.ERR_ARG
     assert "r * n < 2^31" in cur.last_error()
     assert L.cur_select_rect(None, cur.F64, p, 400, 300, 300, 8, 16, ctypes.byref(o), p, p, None) == cur.ERR_ARG
-    assert "no polish" in cur.last_error()
+    assert "polish needs r == c" in cur.last_error()
+    assert L.cur_select_rect(None, cur.F64, p, 400, 300, 300, 8, 8, ctypes.byref(o), p, p, None) == cur.ERR_ARG
+    assert "ctx" in cur.last_error()  # r == c: valid, reaches the context check
     items = (cur.Item * 1)(cur.Item(cur.F64, 3, 1, 10, 12, 12, 1, 1))
     assert L.cur_select_batched(None, 1, items, ctypes.byref(o), None) == cur.ERR_ARG
     assert "no polish" in cur.last_error()

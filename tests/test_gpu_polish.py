@@ -145,3 +145,46 @@ def test_polish_then_plain_selection_reuses_the_context(orc):
     b = cur.select(A, 12, col_block=32)
     np.testing.assert_array_equal(a["I"].cpu().numpy(), b["I"].cpu().numpy())
     np.testing.assert_array_equal(a["J"].cpu().numpy(), b["J"].cpu().numpy())
+
+
+# the symmetric form of Alg. 2 (cur_select_rect, r == c) with the polish:
+# I from the row tree, J from the column tree, then the swap loop on their
+# cross over every column
+RECT_CASES = [
+    (300, 500, 12, 32, 21, torch.float64),
+    (500, 300, 20, 40, 22, torch.float64),
+    (400, 700, 8, 32, 23, torch.float32),
+    (1000, 1500, 64, 64, 24, torch.float64),
+    (600, 900, 100, 128, 25, torch.float64),
+]
+
+
+@pytest.mark.parametrize("m,n,r,w,seed,dt", RECT_CASES)
+def test_rect_polish_matches_oracle(orc, m, n, r, w, seed, dt):
+    A = torch.from_numpy(W.gaussian(m, n, seed)).to(dt).to(DEV)
+    Ah = A.cpu().numpy().astype(np.float64)
+    say(f"rect polish case m={m} n={n} r=c={r} w={w} dtype={dt}")
+    g = cur.select_rect(A, r, r, col_block=w, polish=True)
+    o = orc.select_rect(Ah, r, r, w=w, polish=True)
+    assert g["status"] == o["status"] == cur.OK
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    ps = o["polish"]
+    assert g["nodes"] == o["rows"]["nodes"] + o["cols"]["nodes"] + 1
+    for key in ("swaps", "phases", "refreshes"):
+        assert g[key] == o["rows"][key] + o["cols"][key] + ps[key], key
+    assert abs(g["logvol"] - o["logvol"]) <= 1e-12 * max(1.0, abs(o["logvol"]))
+    dominant(Ah, o["I"], o["J"])
+
+
+def test_rect_polish_skipped_on_a_rank_short_axis(orc):
+    Ah = rand(40, 3, 7) @ rand(3, 60, 8)  # rank 3
+    A = torch.from_numpy(Ah).to(DEV)
+    g = cur.select_rect(A, 5, 5, col_block=8, polish=True)
+    base = cur.select_rect(A, 5, 5, col_block=8)
+    o = orc.select_rect(Ah, 5, 5, w=8, polish=True)
+    assert g["status"] == base["status"] == o["status"] == cur.ERR_RANK
+    assert "polish" not in o
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), base["I"].cpu().numpy())
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), base["J"].cpu().numpy())
+    assert g["nodes"] == base["nodes"] and not np.isfinite(g["logvol"])

@@ -70,3 +70,39 @@ def test_polish_leaves_a_rank_short_root(orc):
     assert pol["nodes"] == base["nodes"]
     # no polish record either
     np.testing.assert_array_equal(pol["trace"]["meta"], base["trace"]["meta"])
+
+
+@pytest.mark.parametrize("shape,r,w,seed", [((150, 260), 8, 32, 31), ((300, 200), 12, 24, 32), ((64, 90), 5, 8, 33)])
+def test_rect_polish_is_dominant_over_the_whole_matrix(orc, shape, r, w, seed):
+    # the symmetric form of Alg. 2: I from the row tree, J from the column
+    # tree, chosen apart; the polish makes the square cross dominant on all
+    # of A (numpy solves over every row and column) and never lowers |det|
+    m, n = shape
+    A = rand(m, r + 5, seed) @ np.diag(0.6 ** np.arange(r + 5)) @ rand(r + 5, n, seed + 10) + 1e-3 * rand(m, n, seed + 20)
+    base = orc.select_rect(A, r, r, w=w)
+    pol = orc.select_rect(A, r, r, w=w, polish=True)
+    assert base["status"] == pol["status"] == 0
+    I, J = pol["I"], pol["J"]
+    assert np.abs(row_interp(A, I, J)).max() <= 1 + 1e-12
+    assert np.abs(col_interp(A, I, J, np.arange(n))).max() <= 1 + 1e-12
+    assert _logvol(A, I, J) >= _logvol(A, base["I"], base["J"]) - 1e-12
+    assert abs(pol["logvol"] - _logvol(A, I, J)) <= 1e-12 * abs(pol["logvol"]) + 1e-12
+    assert list(I) == sorted(I) and list(J) == sorted(J)
+
+
+def test_rect_polish_brute_force_single_swaps(orc):
+    for seed in range(3):
+        A = rand(10, 11, 800 + seed)
+        for r in (1, 2, 3):
+            pol = orc.select_rect(A, r, r, w=max(r, 3), polish=True)
+            assert pol["status"] == 0
+            assert single_swap_gain(A, pol["I"], pol["J"], np.arange(11)) <= 1 + 1e-10
+
+
+def test_rect_polish_applies_to_square_crosses_only(orc):
+    A = rand(80, 90, 41)
+    a = orc.select_rect(A, 4, 6, w=8)
+    b = orc.select_rect(A, 4, 6, w=8, polish=True)
+    assert "polish" not in b
+    np.testing.assert_array_equal(a["I"], b["I"])
+    np.testing.assert_array_equal(a["J"], b["J"])
