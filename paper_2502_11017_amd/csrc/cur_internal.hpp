@@ -76,6 +76,11 @@ struct Node {
   int64_t lda;       // leaves: its leading dimension
   int32_t trans;     // leaves: the tree selects from A^T (its rows are the columns of src)
   int64_t col0;      // leaves: first column of the block
+  void* panel_alt;   // polish node: A^T column-major (n x m, ld n), element T; the panel of
+                     // its column phases, which run as row phases of A^T (panel and panel_alt,
+                     // m and m_alt, ntiles and ntiles_alt trade places at each phase change)
+  int64_t m_alt;     // polish node: rows of the other orientation's panel
+  int32_t ntiles_alt;  // polish node: row tiles of the other orientation
   int64_t tclk[8];   // wall-clock ticks spent in controller steps (diagnostics):
                      // build, col phase, col fresh, col swaps, sort, whole ctl, LU, inverse
   // ---- dynamic state (device) ----
@@ -93,6 +98,7 @@ struct Node {
   double vol_m;      // volume mantissa (finished nodes)
   int32_t vol_e;     // volume exponent
   int32_t lz;        // row swaps pending in the history (their updates are not in `work`)
+  int32_t flipped;   // polish node: 1 while in the A^T orientation (I holds J, Jp holds I)
   int64_t lzi[kLz];  // row swapped in by each pending swap
   int32_t lzk[kLz];  // its slot k
 };

@@ -307,6 +307,7 @@ enum CtlMode : int32_t {
   M_FINISH_SHORT = 104,
   M_REFRESH = 105,
   M_SWAPVEC = 106,
+  M_FLIP = 108,      // polish node: change orientation, then the next phase as a row phase
 };
 
 struct CtlShared {
@@ -400,23 +401,41 @@ __device__ bool ctl_build_impl(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool w
   const int r = nd.r;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
+  // In the A^T orientation (a polish node's column phase) the panel is A^T
+  // and sI / sJp hold J / I, so G = A(I, J) is gathered transposed, and the
+  // fresh kernel is handed X^T: B^T = X A(I, :) row for row.
+  const bool fl = nd.flipped != 0;
   if constexpr (RMAX <= 64) {
     const int64_t tg = wall_clock64();
     LuRegs<RMAX> R;
     const GPtr<const T> Pg = (GPtr<const T>)P;
     const bool okg = lu_fwd_reg<RMAX>(
-        [&](int p, int c) { return (double)Pg[(int64_t)L.sJp[c] * m + L.sI[p]]; }, r, R, L.B, L.lu);
+        [&](int p, int c) {
+          const int64_t i = fl ? L.sI[c] : L.sI[p];
+          const int64_t j = fl ? L.sJp[p] : L.sJp[c];
+          return (double)Pg[j * m + i];
+        },
+        r, R, L.B, L.lu);
     if (threadIdx.x == 0) nd.tclk[6] += wall_clock64() - tg;
     if (!okg) return false;
     if (want_vol && threadIdx.x == 0) lu_volume(L.lu.diag, 1, r, &L.s.vol_m, &L.s.vol_e);
     const int64_t ti = wall_clock64();
     if (want_X) lu_back_reg<RMAX>(r, R, L.B, L.lu, nd.X, L.A);
     __syncthreads();
+    if (want_X && fl) {
+      // X(a, k) is L.A[k RMAX + a]: row k of X^T
+      block_global_sync();
+      for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
+        const int k = idx / r, a = idx % r;
+        nd.X[idx] = L.A[k * RMAX + a];
+      }
+      block_global_sync();
+    }
     if (threadIdx.x == 0) nd.tclk[7] += wall_clock64() - ti;
   } else {
     for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
       const int a = idx / r, b = idx % r;
-      L.A[idx] = (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
+      L.A[idx] = fl ? (double)P[(int64_t)L.sJp[a] * m + L.sI[b]] : (double)P[(int64_t)L.sJp[b] * m + L.sI[a]];
     }
     __syncthreads();
     const int64_t tg = wall_clock64();
@@ -427,9 +446,46 @@ __device__ bool ctl_build_impl(Node& nd, CtlLds<T, RMAX>& L, bool want_X, bool w
     const int64_t ti = wall_clock64();
     if (want_X) block_lu_inverse<CtlLds<T, RMAX>::CH>(L.A, L.perm, r, L.B, nd.X);
     __syncthreads();
+    if (want_X && fl) {  // X (row-major in nd.X) -> X^T, through L.A
+      block_global_sync();
+      for (int idx = threadIdx.x; idx < r * r; idx += kThreads) L.A[idx] = nd.X[idx];
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < r * r; idx += kThreads) {
+        const int k = idx / r, a = idx % r;
+        nd.X[idx] = L.A[a * r + k];
+      }
+      block_global_sync();
+    }
     if (threadIdx.x == 0) nd.tclk[7] += wall_clock64() - ti;
   }
   return true;
+}
+
+// Polish node: trade the A and A^T orientations (I and J, the two panels,
+// their row counts and tile counts).  Every thread reads the orientation
+// before thread 0 changes it.
+template <typename T, int RMAX>
+__device__ void ctl_flip(Node& nd, CtlLds<T, RMAX>& L, int r) {
+  __syncthreads();
+  for (int k = threadIdx.x; k < r; k += kThreads) {
+    const int64_t a = L.sI[k];
+    const int32_t b = L.sJp[k];
+    L.sI[k] = b;
+    L.sJp[k] = (int32_t)a;
+  }
+  if (threadIdx.x == 0) {
+    void* p = nd.panel;
+    nd.panel = nd.panel_alt;
+    nd.panel_alt = p;
+    const int64_t mm = nd.m;
+    nd.m = nd.m_alt;
+    nd.m_alt = mm;
+    const int32_t nt = nd.ntiles;
+    nd.ntiles = nd.ntiles_alt;
+    nd.ntiles_alt = nt;
+    nd.flipped ^= 1;
+  }
+  block_global_sync();
 }
 
 template <typename T, int RMAX>
@@ -462,17 +518,14 @@ __device__ __forceinline__ double ctl_x(const CtlLds<T, RMAX>& L, int r, int a, 
 
 // Fresh column interpolation matrix Bc = X A(I, Jc) (r x nc, row-major, ld ncmax),
 // sums over k ascending, then column Jp[k] := e_k.  X is in L.A.  Chunks of
-// CH columns: A(I, chunk) staged in L.B (a polish node reads the rows of its
-// source matrix, contiguous along the chunk, instead of its column-major
-// panel), then thread (g, j) forms outputs (g + G q, j), q < QM, each a
-// register accumulator over k, so one L.B read serves QM products.
+// CH columns: A(I, chunk) staged in L.B, then thread (g, j) forms outputs
+// (g + G q, j), q < QM, each a register accumulator over k, so one L.B read
+// serves QM products.
 template <typename T, int RMAX>
 __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
   const int r = nd.r, nc = L.s.nc, ld = nd.ncmax, tid = threadIdx.x;
   const int64_t m = nd.m;
   const T* P = (const T*)nd.panel;
-  const T* S = (nd.kind == KIND_POLISH && !nd.trans) ? (const T*)nd.src : nullptr;
-  const int64_t lds = nd.lda;
   constexpr int CH = CtlLds<T, RMAX>::CH;
   constexpr int G = kThreads / CH;            // row groups
   constexpr int QM = (RMAX + G - 1) / G;      // outputs per thread
@@ -488,7 +541,7 @@ __device__ void ctl_fresh_bc(Node& nd, CtlLds<T, RMAX>& L, double* bc) {
     for (int q = 0; q < GL; ++q) {
       const int e = tid + q * kThreads;
       const int k = min(e / CH, r - 1), jj = min(e % CH, nb - 1);
-      st[q] = S ? (double)S[L.sI[k] * lds + c0 + jj] : (double)P[(int64_t)(c0 + jj) * m + L.sI[k]];
+      st[q] = (double)P[(int64_t)(c0 + jj) * m + L.sI[k]];
     }
 #pragma unroll
     for (int q = 0; q < GL; ++q) {
@@ -1009,7 +1062,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
   const int64_t tctl = wall_clock64();
   const int tid = threadIdx.x;
   const int r = nd.r;
-  const int64_t m = nd.m;
+  int64_t m = nd.m;  // a polish node's orientation change swaps it
   const double lim = 1.0 + nd.tau;
   if (tid == 0) {
     CtlShared& s = L.s;
@@ -1195,9 +1248,16 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
           s.mode = M_FINISH;
         } else {
           s.phase++;
-          s.mode = M_COL;
+          // a polish node runs its column phases as row phases of A^T (the
+          // column phase is the row phase of the transpose, element for element)
+          s.mode = (nd.kind == KIND_POLISH) ? M_FLIP : M_COL;
         }
       }
+      __syncthreads();
+    } else if (mode == M_FLIP) {
+      ctl_flip(nd, L, r);
+      m = nd.m;
+      if (tid == 0) L.s.mode = M_ROW_START;
       __syncthreads();
     } else if (mode == M_COL) {
       if constexpr (RMAX <= 64) {
@@ -1209,6 +1269,11 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
         ctl_col_phase(nd, L, lim);
       }
     } else if (mode == M_FINISH) {
+      const bool fl = nd.flipped != 0;
+      if (fl) {  // back to the A orientation for the volume and the outputs
+        ctl_flip(nd, L, r);
+        m = nd.m;
+      }
       ctl_sort_IJ(nd, L, r);
       if (!L.s.err) {
         if (!ctl_build(nd, L, false, true) && tid == 0) L.s.err = 106;
@@ -1580,6 +1645,7 @@ struct TreeJob {
   // indices) over all n columns instead of selecting one
   const int64_t* start_I = nullptr;
   const int64_t* start_J = nullptr;
+  int ntiles_alt = 0;       // polish: row tiles of A^T (n rows)
   cur_status status = CUR_OK;
   bool active = true;
   double theta = 0.0;
@@ -1668,6 +1734,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
       c = (c + 1) / 2;
     }
     jb.ntiles = (int)((jb.m + kTileRows - 1) / kTileRows);
+    jb.ntiles_alt = (jb.polish || jb.start_I) ? (int)((jb.n + kTileRows - 1) / kTileRows) : 0;
     jb.leafmax = 0;
     for (int k = 0; k < jb.b; ++k) {
       const int64_t c0 = (int64_t)k * jb.w, c1 = (k == jb.b - 1) ? jb.n : (int64_t)(k + 1) * jb.w;
@@ -1704,23 +1771,32 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   auto is_polish = [](const TreeJob<T>& jb, int l) {
     return (jb.polish && l + 1 == (int)jb.count.size()) || jb.start_I != nullptr;
   };
+  // a polish node's buffers serve both orientations: B and the swap history
+  // hold max(m, n) rows, the tile winners max of both tile counts, and A^T is
+  // the source itself when its rows are packed (lda == n), else a copy
+  auto rows_of = [&](const TreeJob<T>& jb, int l) { return is_polish(jb, l) ? std::max(jb.m, jb.n) : jb.m; };
+  auto tiles_of = [&](const TreeJob<T>& jb, int l) {
+    return is_polish(jb, l) ? std::max(jb.ntiles, jb.ntiles_alt) : jb.ntiles;
+  };
+  auto alt_copy = [&](const TreeJob<T>& jb, int l) { return is_polish(jb, l) && jb.lda != jb.n; };
   auto node_bytes = [&](const TreeJob<T>& jb, int l) {
     const int nc = jb.ncmax[l], r = jb.r;
     const int wd = is_polish(jb, l) ? r : std::max(nc, r);
-    const int64_t m = jb.m;
+    const int64_t m = jb.m, mr = rows_of(jb, l);
     size_t per = 0;
     per += al(sizeof(T) * m * nc);                // panel
-    per += al(sizeof(double) * m * wd);           // work: ACA residual, then B (FP64)
+    if (alt_copy(jb, l)) per += al(sizeof(T) * jb.n * m);  // A^T for a polish node
+    per += al(sizeof(double) * mr * wd);          // work: ACA residual, then B (FP64)
     per += al(sizeof(double) * r * r);            // X
     per += al(sizeof(double) * r * nc);           // Bc
     per += al(sizeof(double) * (wd + 128 + nc));  // vec (w | rowk)
-    per += al(sizeof(Partial) * jb.ntiles);
+    per += al(sizeof(Partial) * tiles_of(jb, l));
     per += al(sizeof(int64_t) * nc);              // Jc
     per += al(sizeof(int32_t) * nc) * 2;          // colmap, srcpos
     per += al(nc);                                // insel
     per += al(sizeof(int64_t) * r) + al(sizeof(int32_t) * r);
     per += al(sizeof(double) * 4 * kDbgRing);
-    per += al(sizeof(double) * m * kLz);          // swap history: columns g_s
+    per += al(sizeof(double) * mr * kLz);         // swap history: columns g_s
     per += al(sizeof(double) * kLz * r);          // swap history: factors v_s
     return per;
   };
@@ -1749,13 +1825,19 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   int maxm = 0, rmax = 0, leafmax = 0, maxtiles = 0;
   int64_t iter_bound = 0;
   std::vector<RootOut> roots;
+  struct AltCopy {
+    void* dst;
+    const T* src;
+    int64_t n, m, lda;
+  };
+  std::vector<AltCopy> alt_copies;  // A^T panels of polish nodes whose source rows are padded
   for (TreeJob<T>& jb : jobs) {
     if (!jb.active) continue;
     const int r = jb.r;
     maxm = std::max<int>(maxm, (int)std::min<int64_t>(jb.m, INT32_MAX));
     rmax = std::max(rmax, r);
     leafmax = std::max(leafmax, jb.leafmax);
-    maxtiles = std::max(maxtiles, jb.ntiles);
+    maxtiles = std::max(maxtiles, tiles_of(jb, 0));
     iter_bound = std::max<int64_t>(iter_bound, 16 * (int64_t)(r + 4) + 8 * (int64_t)jb.o.max_swaps + 4096);
     for (size_t l = 0; l < jb.count.size(); ++l) {
       const int nc = jb.ncmax[l];
@@ -1770,11 +1852,30 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         nd.tau = jb.o.tau;
         nd.theta = jb.theta;
         nd.panel = ar.take(sizeof(T) * jb.m * nc);
-        nd.work = ar.take(sizeof(double) * jb.m * wd);
+        nd.work = ar.take(sizeof(double) * rows_of(jb, (int)l) * wd);
         nd.X = (double*)ar.take(sizeof(double) * r * r);
         nd.Bc = (double*)ar.take(sizeof(double) * r * nc);
         nd.vec = (double*)ar.take(sizeof(double) * (wd + 128 + nc));
-        nd.part = (Partial*)ar.take(sizeof(Partial) * jb.ntiles);
+        nd.part = (Partial*)ar.take(sizeof(Partial) * tiles_of(jb, (int)l));
+        if (is_polish(jb, (int)l)) {
+          if (jb.trans) {
+            set_error("a polish over a transposed source");
+            return CUR_ERR_INTERNAL;
+          }
+          if (alt_copy(jb, (int)l)) {
+            nd.panel_alt = ar.take(sizeof(T) * jb.n * jb.m);
+            if (!nd.panel_alt) {
+              set_error("workspace layout overflow");
+              return CUR_ERR_INTERNAL;
+            }
+            alt_copies.push_back({nd.panel_alt, jb.A, jb.n, jb.m, jb.lda});
+          } else {
+            nd.panel_alt = const_cast<T*>(jb.A);
+          }
+          nd.m_alt = jb.n;
+          nd.ntiles_alt = jb.ntiles_alt;
+          nd.flipped = 0;
+        }
         nd.Jc = (int64_t*)ar.take(sizeof(int64_t) * nc);
         nd.colmap = (int32_t*)ar.take(sizeof(int32_t) * nc);
         nd.srcpos = (int32_t*)ar.take(sizeof(int32_t) * nc);
@@ -1782,7 +1883,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         nd.I = (int64_t*)ar.take(sizeof(int64_t) * r);
         nd.Jp = (int32_t*)ar.take(sizeof(int32_t) * r);
         nd.dbg = (double*)ar.take(sizeof(double) * 4 * kDbgRing);
-        nd.lzg = ar.take(sizeof(double) * jb.m * kLz);
+        nd.lzg = ar.take(sizeof(double) * rows_of(jb, (int)l) * kLz);
         nd.lzv = (double*)ar.take(sizeof(double) * kLz * r);
         if (!nd.panel || !nd.work || !nd.insel || !nd.Jp || !nd.dbg || !nd.lzv) {
           set_error("workspace layout overflow");
@@ -1841,6 +1942,9 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
   int64_t* d_expI = tr ? (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * rtr) : nullptr;
   int64_t* d_expJ = tr ? (int64_t*)ar.take(sizeof(int64_t) * (size_t)total * rtr) : nullptr;
   CUR_HIP_CHECK(hipMemcpyAsync(d_nodes, h.data(), sizeof(Node) * total, hipMemcpyHostToDevice, s));
+  for (const AltCopy& c : alt_copies)  // A^T column-major (ld n) = the rows of A, packed
+    CUR_HIP_CHECK(hipMemcpy2DAsync(c.dst, sizeof(T) * c.n, c.src, sizeof(T) * c.lda, sizeof(T) * c.n, c.m,
+                                   hipMemcpyDeviceToDevice, s));
   CUR_HIP_CHECK(hipMemcpyAsync(d_roots, roots.data(), sizeof(RootOut) * roots.size(), hipMemcpyHostToDevice, s));
   CUR_HIP_CHECK(hipMemsetAsync(d_done, 0, 4096, s));
   if (ctx->prof_on) CUR_HIP_CHECK(hipMemsetAsync(ctx->prof_bytes, 0, sizeof(unsigned long long) * 2 * kProfSlots, s));
@@ -1893,7 +1997,7 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
     for (const TreeJob<T>& jb : jobs)
       if (jb.active && (int)jb.count.size() > l) {
         lm = std::max<int>(lm, (int)std::min<int64_t>(jb.m, INT32_MAX));
-        lt = std::max(lt, jb.ntiles);
+        lt = std::max(lt, tiles_of(jb, l));
       }
     int32_t* dd = d_done + 16 * l;
     hipLaunchKernelGGL(k_merge_init, dim3(cnt), dim3(kThreads), 0, s, cur, prev);
