@@ -166,6 +166,36 @@ def bench_f1(cur, torch, A, r, res_maxvol, reps=3):
     return out
 
 
+def bench_f2_polish(cur, torch, A, r, res_plain, t_plain, reps=3):
+    """The optional whole-matrix polish on the same C2 matrix: the selection
+    with one more node that runs the swap loop over all columns from the
+    root's cross, its time against the plain selection's, and the volume it
+    gains (the polished cross is dominant over the whole matrix)."""
+    import numpy as np
+
+    cur.select(A, r, polish=True)
+    if t_plain is None:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            cur.select(A, r)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - a) / reps
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        g = cur.select(A, r, polish=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+    out = {"workload": "C2 (same matrix), selection then the swap loop over all 8192 columns from the root's cross",
+           "select_ms": 1e3 * dt, "plain_select_ms": 1e3 * t_plain, "status": g["status"],
+           "polish_swaps": g["swaps"] - res_plain["swaps"], "nodes": g["nodes"],
+           "volume_ratio_vs_plain": float(np.exp(g["logvol"] - res_plain["logvol"]))}
+    log(f"f2: polished selection {1e3 * dt:.1f} ms (plain {1e3 * t_plain:.1f} ms), {out['polish_swaps']} more swaps, "
+        f"volume ratio to the plain cross {out['volume_ratio_vs_plain']:.3e}")
+    return out
+
+
 def bench_e4(cur, torch, A, r, res_plain, t_plain, reps=3):
     """The learned candidate proposal on the same C2 matrix: the selection
     time with the shipped weights (features, scores, restricted starts and
@@ -221,6 +251,7 @@ def main():
     ap.add_argument("--no-e2", action="store_true", help="skip the batched uneven-workload figures")
     ap.add_argument("--no-e4", action="store_true", help="skip the learned-proposal figures")
     ap.add_argument("--no-f1", action="store_true", help="skip the norm-greedy (paper-literal) selection figures")
+    ap.add_argument("--no-f2", action="store_true", help="skip the whole-matrix polish figures")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of the launch autotuner cache: loaded before the run when it exists, "
                          "written at the end (profiling runs reuse the tuned launch shapes)")
@@ -383,6 +414,9 @@ def main():
     f1 = None
     if not args.no_f1:
         f1 = bench_f1(cur, torch, A, r, res)
+    f2 = None
+    if not args.no_f2:
+        f2 = bench_f2_polish(cur, torch, A, r, res, t_sel)
     e1 = None
     if not args.no_e1:
         e1 = bench_e1(cur, W, torch, dev)
@@ -424,6 +458,7 @@ def main():
         "e1_reduced_precision_residual": e1,
         "e2_batched_uneven": e2,
         "f1_paper_greedy": f1,
+        "f2_polish": f2,
         "e4_learned_proposal": e4,
         "cpu_baseline": cpu,
     }
