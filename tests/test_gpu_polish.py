@@ -188,3 +188,27 @@ def test_rect_polish_skipped_on_a_rank_short_axis(orc):
     np.testing.assert_array_equal(g["I"].cpu().numpy(), base["I"].cpu().numpy())
     np.testing.assert_array_equal(g["J"].cpu().numpy(), base["J"].cpu().numpy())
     assert g["nodes"] == base["nodes"] and not np.isfinite(g["logvol"])
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_polish_of_a_padded_matrix(orc, dt):
+    # lda > n: the polish's A^T panel is then a packed copy of A's rows
+    # (with lda == n it is A itself); both selection paths must equal the
+    # oracle on the packed matrix
+    m, n, pad = 600, 900, 13
+    Ah = W.gaussian(m, n, 44)
+    big = torch.zeros((m, n + pad), dtype=dt, device=DEV)
+    big[:, :n] = torch.from_numpy(Ah).to(dt).to(DEV)
+    A = big[:, :n]
+    assert A.stride(0) == n + pad
+    Ap = A.contiguous().cpu().numpy().astype(np.float64)
+    say(f"padded polish case m={m} n={n} lda={n + pad} dtype={dt}")
+    g = cur.select(A, 16, col_block=64, polish=True, trace=True)
+    o = orc.select(Ap, 16, w=64, polish=True, trace=True)
+    same(g, o)
+    g = cur.select_rect(A, 16, 16, col_block=64, polish=True)
+    o = orc.select_rect(Ap, 16, 16, w=64, polish=True)
+    assert g["status"] == o["status"]
+    np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
+    np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
+    assert abs(g["logvol"] - o["logvol"]) <= 1e-12 * max(1.0, abs(o["logvol"]))
