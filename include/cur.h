@@ -106,7 +106,8 @@ typedef struct {
                           further record and no node counted.  cur_select_rect with r == c:
                           the same loop on the cross (I, J) of its two trees (the symmetric
                           form of Alg. 2), skipped if either tree falls short; info.logvol
-                          is then that cross's.  cur_select_batched rejects it.          */
+                          is then that cross's.  cur_select_batched: every item's tree
+                          gets its polish level.                                         */
 } cur_opts;
 
 typedef struct {

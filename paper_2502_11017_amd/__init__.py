@@ -457,8 +457,10 @@ def tune_import(entries, device=None):
     _check(lib().cur_tune_import(context(device), buf, len(entries)))
 
 
-def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, groups: int = 0):
-    """Independent selections of several device matrices (cur_select_batched)."""
+def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int = 0, groups: int = 0,
+                   polish: bool = False):
+    """Independent selections of several device matrices (cur_select_batched);
+    polish: each tree's root polished over all its matrix's columns."""
     torch = _torch()
     cnt = len(As)
     items = (Item * max(cnt, 1))()
@@ -470,7 +472,7 @@ def select_batched(As, rs, col_block: int = 0, tau: float = 0.0, max_swaps: int 
         items[k] = Item(_dtype_code(A), int(r), A.data_ptr(), m, n, lda, I.data_ptr(), J.data_ptr())
         outs.append((I, J))
     per = (ctypes.c_int * max(cnt, 1))()
-    o = make_opts(col_block, tau, max_swaps, groups=groups)
+    o = make_opts(col_block, tau, max_swaps, groups=groups, polish=polish)
     ctx = context(As[0].device.index if cnt else None)
     rc = lib().cur_select_batched(ctx, cnt, items, ctypes.byref(o), per)
     _check(rc, (OK, WARN_NOCONV, ERR_RANK))

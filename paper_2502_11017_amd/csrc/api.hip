@@ -467,8 +467,6 @@ cur_status cur_select_batched(cur_ctx ctx, int32_t count, const cur_item* items,
     return arg_error("batched selection supports the maximal-volume method only");
   if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->propose != 0)
     return arg_error("batched selection supports no candidate proposal");
-  if (opts && opts->struct_size == (int32_t)sizeof(cur_opts) && opts->polish != 0)
-    return arg_error("batched selection supports no polish");
   for (int32_t i = 0; i < count; ++i) {
     const cur_item& it = items[i];
     cur_status st = check_matrix(it.dtype, it.A, it.m, it.n, it.lda, it.r);

@@ -2292,6 +2292,7 @@ static cur_status select_group(cur_ctx ctx, int rb, const std::vector<int>& idx,
     jb.I = it.I;
     jb.J = it.J;
     jb.info = nullptr;
+    jb.polish = jb.o.polish != 0;
   }
   cur_status rc = select_many<T>(ctx, rb, jobs, nullptr);
   for (size_t q = 0; q < idx.size(); ++q) per_item[idx[q]] = rc != CUR_OK ? rc : jobs[q].status;

@@ -212,3 +212,27 @@ def test_polish_of_a_padded_matrix(orc, dt):
     np.testing.assert_array_equal(g["I"].cpu().numpy(), o["I"])
     np.testing.assert_array_equal(g["J"].cpu().numpy(), o["J"])
     assert abs(g["logvol"] - o["logvol"]) <= 1e-12 * max(1.0, abs(o["logvol"]))
+
+
+def test_batched_polish_equals_single_calls(orc):
+    # one engine run for trees of different depths, shapes, dtypes and rank
+    # buckets, each with its polish level (at different level indices), and a
+    # rank-short item whose polish does nothing
+    shapes = [(300, 500, 12, torch.float64), (700, 260, 20, torch.float64), (256, 1100, 8, torch.float32),
+              (500, 700, 40, torch.float64), (640, 900, 70, torch.float64)]
+    As = [torch.from_numpy(W.gaussian(m, n, 60 + k)).to(dt).to(DEV) for k, (m, n, r, dt) in enumerate(shapes)]
+    rs = [r for (_, _, r, _) in shapes]
+    As.append(torch.from_numpy(rand(50, 3, 61) @ rand(3, 80, 62)).to(DEV))  # rank 3
+    rs.append(6)
+    say(f"batched polish: {len(As)} items")
+    outs, _ = cur.select_batched(As, rs, polish=True)
+    for k, (A, r) in enumerate(zip(As, rs)):
+        g = cur.select(A, r, polish=True)
+        I, J, st = outs[k]
+        assert st == g["status"], (k, st, g["status"])
+        np.testing.assert_array_equal(I.cpu().numpy(), g["I"].cpu().numpy())
+        np.testing.assert_array_equal(J.cpu().numpy(), g["J"].cpu().numpy())
+        if k in (0, 2, 5):
+            o = orc.select(A.cpu().numpy().astype(np.float64), r, polish=True)
+            assert o["status"] == st
+            np.testing.assert_array_equal(I.cpu().numpy()[:o["rank"]], o["I"][:o["rank"]])
