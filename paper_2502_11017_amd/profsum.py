@@ -108,7 +108,9 @@ def level_table(path, skip=0):
             sels.append(cur_sel)
         if cur_sel is None:
             continue
-        if "k_panel_from_A" in name or "k_merge_init" in name:
+        # a level starts at the leaves' panel copy or at a merge set-up (a
+        # polish level's panel copy follows its merge set-up: same level)
+        if ("k_panel_from_A" in name and not cur_sel) or "k_merge_init" in name:
             cur_sel.append([])
         if cur_sel:
             cur_sel[-1].append((name, int(r["Start_Timestamp"]), int(r["End_Timestamp"])))

@@ -71,6 +71,23 @@ def test_level_table_splits_selections_and_levels(tmp_path):
     assert out[4].split()[0] == "all"
 
 
+def test_level_table_keeps_a_polish_panel_copy_in_its_level(tmp_path):
+    """A polish level copies its panel after its merge set-up: one level, not two."""
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = [["void cur::k_amax<double>(...)", 0, 1000],
+            ["void cur::k_panel_from_A<double>(...)", 2000, 3000],
+            ["void cur::k_ctl<double, 64>(...)", 4000, 5000],
+            ["cur::k_merge_init(...)", 6000, 7000],
+            ["void cur::k_panel_from_A<double>(...)", 7000, 9000],
+            ["void cur::k_ctl<double, 64>(...)", 9000, 10000]]
+    p = tmp_path / "t.csv"
+    _write(p, hdr, rows)
+    out = profsum.level_table(str(p)).splitlines()
+    assert out[0].startswith("1 selection(s), 2 levels")
+    lv1 = out[3].split()
+    assert lv1[:2] == ["1", "0.004"] and lv1[7] == "3"
+
+
 def test_mfma_table_flops_and_busy_share(tmp_path):
     hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
     rows = []
