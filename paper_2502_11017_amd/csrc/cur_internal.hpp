@@ -28,6 +28,8 @@ enum NodeState : int32_t {
   ST_ROW_FRESH = 2,  // next pass: B = A(:,J) X fresh, then argmax
   ST_ROW_SWAP = 3,   // next pass: apply pending row swap to B, then argmax
   ST_START_SWAP = 4, // next ctl: start the swap loop (ROW phase start)
+  ST_DEFER = 5,      // a controller step with an r x r factorization (or a column phase) is
+                     // due (pend_mode); it waits for a launch that admits such steps
 };
 
 // KIND_POLISH: one node after a tree's root whose candidates are all n columns,
@@ -99,6 +101,7 @@ struct Node {
   int32_t vol_e;     // volume exponent
   int32_t lz;        // row swaps pending in the history (their updates are not in `work`)
   int32_t flipped;   // polish node: 1 while in the A^T orientation (I holds J, Jp holds I)
+  int32_t pend_mode; // ST_DEFER: the controller step to resume
   int64_t lzi[kLz];  // row swapped in by each pending swap
   int32_t lzk[kLz];  // its slot k
 };

@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
+#include <array>
 #include <vector>
 
 #include "cur_device.hpp"
@@ -312,6 +313,7 @@ enum CtlMode : int32_t {
 
 struct CtlShared {
   int mode;
+  int pend_mode;
   int stale;
   int st, t, q, na, steps, nc;
   int is_short, nocap, err, phase, phase_swaps, since, swaps, phases, refreshes;
@@ -1049,7 +1051,7 @@ __device__ void ctl_col_phase_reg(Node& nd, CtlLds<T, RMAX>& L, double lim) {
 }
 
 template <typename T, int RMAX>
-__global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, int startup) {
+__global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, int startup, int heavy_ok) {
   Node& nd = nodes[blockIdx.x];
   if (nd.st == ST_DONE) {
     // a node finished by its initialization is counted once, at start-up
@@ -1058,6 +1060,12 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
   }
   // the start-up launch only opens swap loops; pass states wait for their pass
   if (startup && nd.st != ST_START_SWAP) return;
+  // Steps with an r x r factorization (phase starts, refreshes, column phases,
+  // the final volume) run only in launches that admit them (heavy_ok), so
+  // that the nodes of a level take them together rather than each holding up
+  // a different lock-step iteration; a node that reaches one otherwise waits
+  // in ST_DEFER.  The arithmetic and its order are the same either way.
+  if (nd.st == ST_DEFER && !heavy_ok) return;
   __shared__ CtlLds<T, RMAX> L;
   const int64_t tctl = wall_clock64();
   const int tid = threadIdx.x;
@@ -1071,6 +1079,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     s.phase_swaps = nd.phase_swaps; s.since = nd.since; s.swaps = nd.swaps; s.phases = nd.phases;
     s.refreshes = nd.refreshes; s.pend_k = nd.pend_k; s.pend_i = nd.pend_i; s.pend_p = nd.pend_p;
     s.vol_m = nd.vol_m; s.vol_e = nd.vol_e;
+    s.pend_mode = nd.pend_mode;
     // the pass that just ran: a fresh B empties the swap history; a swap pass
     // added one swap to it, or wrote B out with all of them (the last slot)
     s.lz = nd.lz;
@@ -1189,7 +1198,36 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
       __syncthreads();
       if (tid == 0) L.s.mode = M_EXIT;
       __syncthreads();
-    } else if (L.s.mode == M_REFRESH) {
+    }
+  } else if (st0 == ST_START_SWAP) {
+    if (tid == 0) {
+      L.s.phase = 0;
+      L.s.mode = M_ROW_START;
+    }
+    __syncthreads();
+  } else if (st0 == ST_DEFER) {
+    if (tid == 0) L.s.mode = L.s.pend_mode;
+    __syncthreads();
+  }
+
+  // ---- serial steps until a pass is needed or the node is finished
+  for (int guard = 0; guard < 64; ++guard) {
+    const int mode = L.s.mode;
+    // every wavefront holds this step's mode before thread 0 may overwrite it
+    // (a late wavefront would otherwise take the next step's branch and run
+    // one barrier out of step with the rest of the block)
+    __syncthreads();
+    if (mode == M_EXIT) break;
+    if (!heavy_ok && (mode == M_ROW_START || mode == M_REFRESH || mode == M_COL || mode == M_FINISH)) {
+      if (tid == 0) {
+        L.s.pend_mode = mode;
+        L.s.st = ST_DEFER;
+        L.s.mode = M_EXIT;
+      }
+      __syncthreads();
+      break;
+    }
+    if (mode == M_REFRESH) {
       // tentative stop after swaps: recompute B fresh for the current orders
       if (!ctl_build(nd, L, true, false)) {
         if (tid == 0) {
@@ -1203,24 +1241,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
         L.s.mode = M_EXIT;
       }
       __syncthreads();
-    }
-  } else if (st0 == ST_START_SWAP) {
-    if (tid == 0) {
-      L.s.phase = 0;
-      L.s.mode = M_ROW_START;
-    }
-    __syncthreads();
-  }
-
-  // ---- serial steps until a pass is needed or the node is finished
-  for (int guard = 0; guard < 64; ++guard) {
-    const int mode = L.s.mode;
-    // every wavefront holds this step's mode before thread 0 may overwrite it
-    // (a late wavefront would otherwise take the next step's branch and run
-    // one barrier out of step with the rest of the block)
-    __syncthreads();
-    if (mode == M_EXIT) break;
-    if (mode == M_ROW_START) {
+    } else if (mode == M_ROW_START) {
       ctl_sort_IJ(nd, L, r);
       if (tid == 0) {
         L.s.phase_swaps = 0;
@@ -1319,6 +1340,7 @@ __global__ __launch_bounds__(kThreads) void k_ctl(Node* nodes, int32_t* done, in
     nd.refreshes = s.refreshes; nd.pend_k = s.pend_k; nd.pend_i = s.pend_i; nd.pend_p = s.pend_p;
     nd.vol_m = s.vol_m; nd.vol_e = s.vol_e;
     nd.lz = s.lz;
+    nd.pend_mode = s.pend_mode;
   }
 }
 
@@ -1369,8 +1391,8 @@ struct SelectPlan {
 static int rmax_bucket(int r) { return r <= 32 ? 32 : (r <= 64 ? 64 : 128); }
 
 template <typename T, int RMAX>
-static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
-  hipLaunchKernelGGL((k_ctl<T, RMAX>), dim3(count), dim3(kThreads), 0, s, nodes, done, startup);
+static void launch_ctl(Node* nodes, int count, int32_t* done, int startup, int heavy_ok, hipStream_t s) {
+  hipLaunchKernelGGL((k_ctl<T, RMAX>), dim3(count), dim3(kThreads), 0, s, nodes, done, startup, heavy_ok);
 }
 
 
@@ -1414,10 +1436,10 @@ static void row_launch(cur_ctx ctx, int kind, int rb, Node* nodes, int count, in
 }
 
 template <typename T>
-static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, hipStream_t s) {
-  if (rb == 32) launch_ctl<T, 32>(nodes, count, done, startup, s);
-  else if (rb == 64) launch_ctl<T, 64>(nodes, count, done, startup, s);
-  else launch_ctl<T, 128>(nodes, count, done, startup, s);
+static void ctl_any(int rb, Node* nodes, int count, int32_t* done, int startup, int heavy_ok, hipStream_t s) {
+  if (rb == 32) launch_ctl<T, 32>(nodes, count, done, startup, heavy_ok, s);
+  else if (rb == 64) launch_ctl<T, 64>(nodes, count, done, startup, heavy_ok, s);
+  else launch_ctl<T, 128>(nodes, count, done, startup, heavy_ok, s);
 }
 
 // Streams and events of the node groups, created once per context.
@@ -1491,6 +1513,26 @@ static void tune_record(cur_ctx ctx, const int64_t key[6], int cand, std::chrono
 // a column phase) then holds back only its own group, and its latency-bound
 // controller launch overlaps the other groups' streaming passes.  Groups
 // share no node data; all ordering is by stream order within a group.
+// Controller launches admit steps with an r x r factorization once every P
+// launches (P = 1: every launch), P by the number of nodes sharing the
+// launches: >= 32, >= 8, >= 2, 1.  CUR_GATE="a,b,c,d" sets the four periods.
+static int gate_period(int nodes) {
+  static const std::array<int, 4> per = [] {
+    std::array<int, 4> p = {12, 8, 4, 1};
+    if (const char* e = std::getenv("CUR_GATE")) {
+      int k = 0;
+      for (const char* q = e; *q && k < 4; ++k) {
+        p[k] = std::max(1, std::atoi(q));
+        while (*q && *q != ',') ++q;
+        if (*q == ',') ++q;
+      }
+      for (; k < 4; ++k) p[k] = p[k - 1];
+    }
+    return p;
+  }();
+  return nodes >= 32 ? per[0] : nodes >= 8 ? per[1] : nodes >= 2 ? per[2] : per[3];
+}
+
 template <typename T>
 static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int tiles, int32_t* d_done,
                             int64_t max_iters, size_t& prof_used, int groups) {
@@ -1517,7 +1559,7 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
   }
   volatile int32_t* h = ctx->host_flag;
   for (int g = 0; g < G; ++g)  // start-up decisions
-    ctl_any<T>(rb, nodes + off[g], off[g + 1] - off[g], d_done + g, 1, gs[g]);
+    ctl_any<T>(rb, nodes + off[g], off[g + 1] - off[g], d_done + g, 1, 1, gs[g]);
   const int K = 4;
   int64_t it = 0;
   cur_status rc = CUR_OK;
@@ -1526,10 +1568,11 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
       if (fin[g]) continue;
       Node* gn = nodes + off[g];
       const int gc = off[g + 1] - off[g];
+      const int P = gate_period(gc);
       for (int j = 0; j < K; ++j) {
         row_launch<T>(ctx, 1, rb, gn, gc, tiles, gs[g], prof_used);
         row_launch<T>(ctx, 0, rb, gn, gc, tiles, gs[g], prof_used);
-        ctl_any<T>(rb, gn, gc, d_done + g, 0, gs[g]);
+        ctl_any<T>(rb, gn, gc, d_done + g, 0, (int)((it + j) % P == P - 1), gs[g]);
       }
     }
     it += K;
