@@ -1563,6 +1563,12 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
   const int K = 4;
   int64_t it = 0;
   cur_status rc = CUR_OK;
+  // A node enters the fresh-B state only in a controller launch that admits
+  // factorization steps (a phase start or a refresh builds X), and leaves it
+  // at the next controller launch; so the fresh kernel has work only in the
+  // iteration after such a launch (the start-up launch is one).
+  bool fresh_due[kMaxGroups];
+  for (int g = 0; g < G; ++g) fresh_due[g] = true;
   for (;;) {
     for (int g = 0; g < G; ++g) {
       if (fin[g]) continue;
@@ -1570,9 +1576,11 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
       const int gc = off[g + 1] - off[g];
       const int P = gate_period(gc);
       for (int j = 0; j < K; ++j) {
-        row_launch<T>(ctx, 1, rb, gn, gc, tiles, gs[g], prof_used);
+        const bool heavy = (it + j) % P == P - 1;
+        if (fresh_due[g]) row_launch<T>(ctx, 1, rb, gn, gc, tiles, gs[g], prof_used);
         row_launch<T>(ctx, 0, rb, gn, gc, tiles, gs[g], prof_used);
-        ctl_any<T>(rb, gn, gc, d_done + g, 0, (int)((it + j) % P == P - 1), gs[g]);
+        ctl_any<T>(rb, gn, gc, d_done + g, 0, heavy ? 1 : 0, gs[g]);
+        fresh_due[g] = heavy;
       }
     }
     it += K;

@@ -377,7 +377,9 @@ def test_tune_cache_round_trip():
 def test_profile_counters_count_the_pass_bytes():
     """Level 1 times the streaming pass only, level 2 adds the fresh kernel;
     the algorithmic bytes of one selection are a fixed sum over its launches,
-    and a busy launch is one that moved bytes."""
+    and a busy launch is one that moved bytes.  The fresh kernel is launched
+    only in iterations after a controller launch that admits factorization
+    steps, so it has at most as many launches as the pass."""
     say("case profile counters")
     A = torch.from_numpy(W.gaussian(1000, 640, 23)).to(DEV)
     cur.select(A, 16, groups=1)
@@ -392,7 +394,7 @@ def test_profile_counters_count_the_pass_bytes():
     assert p1["bytes"] > 0 and p1["seconds"] > 0
     assert p1["fresh_launches"] == 0 and p1["fresh_bytes"] == 0
     assert p2["bytes"] == p1["bytes"] and p2["launches"] == p1["launches"]
-    assert p2["fresh_launches"] == p2["launches"] and 0 < p2["fresh_busy"] <= p2["fresh_launches"]
+    assert 0 < p2["fresh_busy"] <= p2["fresh_launches"] <= p2["launches"]
     assert p2["fresh_bytes"] > 0
 
 
