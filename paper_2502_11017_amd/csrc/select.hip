@@ -1518,7 +1518,7 @@ static void tune_record(cur_ctx ctx, const int64_t key[6], int cand, std::chrono
 // launches: >= 32, >= 8, >= 2, 1.  CUR_GATE="a,b,c,d" sets the four periods.
 static int gate_period(int nodes) {
   static const std::array<int, 4> per = [] {
-    std::array<int, 4> p = {12, 8, 4, 1};
+    std::array<int, 4> p = {16, 12, 6, 1};
     if (const char* e = std::getenv("CUR_GATE")) {
       int k = 0;
       for (const char* q = e; *q && k < 4; ++k) {
