@@ -516,3 +516,37 @@ def test_tree_shape_and_merge_tie_golden(case, dt):
     g = cur.select(A, case["r"], col_block=case["w"], trace=True)
     assert g["status"] == cur.OK
     check_tree_golden(case, g["I"].cpu().numpy(), g["J"].cpu().numpy(), g["trace"], g["logvol"])
+
+
+def test_gate_periods_do_not_change_the_selection(orc):
+    """The controller's factorization steps run only in one launch of P; the
+    period changes when they run, never their operands or order.  Selections
+    in child processes with no gating and with other periods equal the
+    oracle's (the variable is read once per process)."""
+    import json
+    import subprocess
+
+    import tempfile
+
+    n = 1536
+    Ah = W.c2(40, device=DEV, n=n).cpu().numpy()
+    o = orc.select(Ah, 32)
+    tmp = tempfile.NamedTemporaryFile(suffix=".npy", delete=False)
+    tmp.close()
+    np.save(tmp.name, Ah)
+    code = ("import json, sys, numpy, torch; sys.path.insert(0, %r); import paper_2502_11017_amd as cur; "
+            "A = torch.from_numpy(numpy.load(%r)).to('cuda:0'); "
+            "g = cur.select(A, 32, groups=2); print(json.dumps({'I': g['I'].tolist(), 'J': g['J'].tolist(), "
+            "'swaps': g['swaps'], 'phases': g['phases'], 'refreshes': g['refreshes']}))"
+            % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), tmp.name))
+    for gate in ("1", "24,16,8,2", "3"):
+        say(f"  child process with CUR_GATE={gate}")
+        env = dict(os.environ, CUR_GATE=gate)
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+        assert out.returncode == 0, out.stderr[-2000:]
+        g = json.loads(out.stdout.strip().splitlines()[-1])
+        np.testing.assert_array_equal(np.array(g["I"]), o["I"])
+        np.testing.assert_array_equal(np.array(g["J"]), o["J"])
+        for key in ("swaps", "phases", "refreshes"):
+            assert g[key] == o[key], (gate, key, g[key], o[key])
+    os.unlink(tmp.name)
