@@ -367,6 +367,11 @@ def main():
                 "launches_per_step": prof[pre + "launches"] / prof_steps,
                 "busy_launches_per_step": prof[pre + "busy"] / prof_steps,
                 "avg_launch_us": 1e6 * sec / n_l,
+                # context: the same bytes over the busy launches only (a
+                # launch that finds no node in its state returns at once)
+                "achieved_busy_launches_gbs": (b_model / prof[pre + "busy_seconds"] / 1e9
+                                               if prof[pre + "busy_seconds"] > 0 else 0.0),
+                "avg_busy_launch_us": 1e6 * prof[pre + "busy_seconds"] / max(prof[pre + "busy"], 1),
                 "timed_steps_with_events": prof_steps}
 
     roof_pass, roof_fresh = roof("pass"), roof("fresh")

@@ -355,6 +355,8 @@ typedef struct {
   double fresh_bytes;
   double bytes_inplace;        /* summed in-place-algorithm bytes, pass launches  */
   double fresh_bytes_inplace;  /* the same for the fresh launches                 */
+  double busy_seconds;         /* summed event time of the busy pass launches     */
+  double fresh_busy_seconds;   /* the same for the fresh launches                 */
 } cur_profile;
 
 /* The launch-shape autotuner cache of a context (cur_opts.groups == 0).  One

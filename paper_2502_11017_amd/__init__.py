@@ -70,7 +70,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("busy", ctypes.c_int64), ("seconds", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("fresh_launches", ctypes.c_int64), ("fresh_busy", ctypes.c_int64),
                 ("fresh_seconds", ctypes.c_double), ("fresh_bytes", ctypes.c_double),
-                ("bytes_inplace", ctypes.c_double), ("fresh_bytes_inplace", ctypes.c_double)]
+                ("bytes_inplace", ctypes.c_double), ("fresh_bytes_inplace", ctypes.c_double),
+                ("busy_seconds", ctypes.c_double), ("fresh_busy_seconds", ctypes.c_double)]
 
 
 class Item(ctypes.Structure):
@@ -434,7 +435,8 @@ def profile_read(device=None) -> dict:
             "bytes_inplace": p.bytes_inplace,
             "fresh_launches": p.fresh_launches, "fresh_busy": p.fresh_busy,
             "fresh_seconds": p.fresh_seconds, "fresh_bytes": p.fresh_bytes,
-            "fresh_bytes_inplace": p.fresh_bytes_inplace}
+            "fresh_bytes_inplace": p.fresh_bytes_inplace,
+            "busy_seconds": p.busy_seconds, "fresh_busy_seconds": p.fresh_busy_seconds}
 
 
 def tune_export(device=None) -> list:

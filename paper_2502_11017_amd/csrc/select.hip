@@ -2095,12 +2095,14 @@ static cur_status select_many(cur_ctx ctx, int rb, std::vector<TreeJob<T>>& jobs
         p.fresh_launches += 1;
         p.fresh_busy += b > 0;
         p.fresh_seconds += 1e-3 * ms;
+        if (b > 0) p.fresh_busy_seconds += 1e-3 * ms;
         p.fresh_bytes += (double)b;
         p.fresh_bytes_inplace += (double)bm;
       } else {
         p.launches += 1;
         p.busy += b > 0;
         p.seconds += 1e-3 * ms;
+        if (b > 0) p.busy_seconds += 1e-3 * ms;
         p.bytes += (double)b;
         p.bytes_inplace += (double)bm;
       }

@@ -395,6 +395,7 @@ def test_profile_counters_count_the_pass_bytes():
     assert p1["fresh_launches"] == 0 and p1["fresh_bytes"] == 0
     assert p2["bytes"] == p1["bytes"] and p2["launches"] == p1["launches"]
     assert 0 < p2["fresh_busy"] <= p2["fresh_launches"] <= p2["launches"]
+    assert 0 < p1["busy_seconds"] <= p1["seconds"] and 0 < p2["fresh_busy_seconds"] <= p2["fresh_seconds"]
     assert p2["fresh_bytes"] > 0
 
 
