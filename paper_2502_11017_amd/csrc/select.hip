@@ -1560,7 +1560,11 @@ static cur_status run_level(cur_ctx ctx, int rb, Node* nodes, int count, int til
   volatile int32_t* h = ctx->host_flag;
   for (int g = 0; g < G; ++g)  // start-up decisions
     ctl_any<T>(rb, nodes + off[g], off[g + 1] - off[g], d_done + g, 1, 1, gs[g]);
-  const int K = 4;
+  // iterations issued between two polls of the done counters
+  static const int K = [] {
+    const char* e = std::getenv("CUR_POLL_ITERS");
+    return e ? std::max(1, std::min(64, std::atoi(e))) : 4;
+  }();
   int64_t it = 0;
   cur_status rc = CUR_OK;
   // A node enters the fresh-B state only in a controller launch that admits
