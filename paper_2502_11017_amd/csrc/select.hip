@@ -1526,7 +1526,7 @@ static int gate_period(int nodes) {
         while (*q && *q != ',') ++q;
         if (*q == ',') ++q;
       }
-      for (; k < 4; ++k) p[k] = p[k - 1];
+      for (; k > 0 && k < 4; ++k) p[k] = p[k - 1];  // fewer values: repeat the last
     }
     return p;
   }();
