@@ -551,3 +551,33 @@ def test_gate_periods_do_not_change_the_selection(orc):
         for key in ("swaps", "phases", "refreshes"):
             assert g[key] == o[key], (gate, key, g[key], o[key])
     os.unlink(tmp.name)
+
+
+def test_compute_unit_mask_does_not_change_selection(orc):
+    """The compute-unit sweep (strong scaling over CUs, after the scalability
+    experiment of Sec. 3.2) runs each count in a child process restricted by
+    the runtime's CU mask.  The CUs a selection runs on change its time,
+    never its result: every count's I, J equal the oracle's."""
+    import hashlib
+    import shutil
+    import tempfile
+
+    from paper_2502_11017_amd import cusweep
+
+    n, r = 1536, 32
+    Ah = W.c2(41, device=DEV, n=n).cpu().numpy()
+    o = orc.select(Ah, r)
+    want = hashlib.sha256(np.asarray(o["I"], dtype=np.int64).tobytes()
+                          + np.asarray(o["J"], dtype=np.int64).tobytes()).hexdigest()[:16]
+    work = tempfile.mkdtemp(prefix="cusweep_test_")
+    try:
+        np.save(os.path.join(work, f"c2_{n}.npy"), Ah)  # the sweep's own file name: no generation step
+        say(f"case cu sweep n={n} r={r} cus=(32, 256)")
+        rows = cusweep.sweep(n=n, r=r, cus=(32, 256), steps=1, warmup=1, workdir=work)
+    finally:
+        shutil.rmtree(work, ignore_errors=True)
+    assert [x["cus"] for x in rows] == [32, 256]
+    for x in rows:
+        assert x["status"] == cur.OK, x
+        assert x["swaps"] == o["swaps"], (x, o["swaps"])
+        assert x["digest"] == want, (x, want)
