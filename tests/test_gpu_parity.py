@@ -326,6 +326,14 @@ def test_select_batched_mixed_trees_match_single(orc):
             np.testing.assert_array_equal(J.cpu().numpy(), o["J"])
         if seed == 0:
             assert st == cur.ERR_RANK
+    # a second call of the same batch (workspace, streams and tuner entries
+    # reused) gives the same results
+    outs2, rc2 = cur.select_batched(As, rs)
+    assert rc2 == rc
+    for (I, J, st), (I2, J2, st2) in zip(outs, outs2):
+        assert st2 == st
+        np.testing.assert_array_equal(I2.cpu().numpy(), I.cpu().numpy())
+        np.testing.assert_array_equal(J2.cpu().numpy(), J.cpu().numpy())
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
